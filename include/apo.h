@@ -1,0 +1,175 @@
+/*
+ * apo.h -- C ABI of libapo.so, the gfx950 (MI355X) implementation of the
+ * Artificial Protozoa Optimizer (APO) population step.
+ *
+ * The calls follow Algorithm 1 of "cuAPO: A CUDA-based Parallelization of
+ * Artificial Protozoa Optimizer": its input (np, ps, dim, pf_max and the
+ * iteration budget) is apo_create's argument list, one pass of its loop
+ * body (sort, pf, Dr, the per-protozoan update of Eqs. (1)-(13), bound
+ * clamp, evaluation, greedy selection) is apo_step, and its output
+ * (f(X_gbest), X_gbest) is apo_best.
+ *
+ * Conventions shared by every call:
+ *   - Plain C types only.  "host" pointers are ordinary CPU memory, "device"
+ *     pointers are HIP device memory of the current device.
+ *   - Return value: APO_OK (0) or a negative apo_status.  No call throws.
+ *   - Host input arrays are copied during the call; the caller keeps
+ *     ownership and may free them on return.  Host output arrays are
+ *     written by the call and owned by the caller.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - After APO_E_DEVICE a handle is poisoned: every call except
+ *     apo_destroy returns APO_E_DEVICE.
+ *   - Population layout seen through the ABI: X is [pop][dim] row-major in
+ *     protozoan-id order (ids are fixed at creation and never move).
+ */
+#ifndef APO_H
+#define APO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct apo apo_t;   /* opaque handle, owned by the caller until apo_destroy */
+
+typedef enum {
+    APO_OK = 0,
+    APO_E_INVAL = -1,        /* an argument is out of range or inconsistent      */
+    APO_E_NOMEM = -2,        /* host or device allocation failed                 */
+    APO_E_DEVICE = -3,       /* a HIP call failed; the handle is poisoned        */
+    APO_E_DONE = -4,         /* the iteration budget is spent; state unchanged   */
+    APO_E_STATE = -5,        /* the handle cannot serve this call (e.g. no trace)*/
+    APO_E_UNSUPPORTED = -6   /* valid arguments outside the sizes built for      */
+} apo_status;
+
+typedef enum {
+    APO_FP64 = 0,            /* positions and fitness in binary64 */
+    APO_FP32 = 1             /* positions and fitness in binary32 */
+} apo_precision;
+
+typedef enum {
+    APO_SPHERE = 0,          /* sum z^2 (Eq. (14))                                   */
+    APO_RASTRIGIN = 1,       /* sum (z^2 - 10 cos(2 pi z) + 10)                      */
+    APO_ROSENBROCK = 2,      /* textbook Rosenbrock on z + 1 (minimum at x = o)      */
+    APO_ACKLEY = 3,          /* textbook Ackley                                      */
+    APO_KAPUR = 4,           /* minus Kapur entropy of a 256-bin histogram, dim thresholds */
+    APO_OTSU = 5             /* minus Otsu between-class variance, dim thresholds    */
+} apo_obj_kind;
+
+/* Objective.  For the first four kinds z = M (x - o): shift o is host
+ * [dim] (NULL: o = 0), rot M is host [dim*dim] row-major (NULL: M = I),
+ * so z_i = sum_j M[i][j] (x_j - o_j).  For APO_KAPUR / APO_OTSU, hist is a
+ * host [256] grey-level histogram (not all zero), each coordinate is a
+ * threshold rounded half-to-even to a grey level and the bounds must lie
+ * in [0, 255]; shift and rot must be NULL. */
+typedef struct {
+    int32_t kind;             /* apo_obj_kind */
+    const double *shift;      /* host [dim] or NULL            (copied) */
+    const double *rot;        /* host [dim*dim] or NULL        (copied) */
+    const uint64_t *hist;     /* host [256] for KAPUR / OTSU   (copied) */
+} apo_objective;
+
+enum {
+    APO_FLAG_TRACE = 1u       /* keep every candidate of the last step for apo_get_trace */
+};
+
+typedef struct {
+    int32_t max_iter;         /* iter_max (T) >= 1: Eqs. (4), (9), (12) use t/T    */
+    int32_t precision;        /* apo_precision                                    */
+    apo_objective objective;
+    uint32_t run_id;          /* fourth Philox counter word (independent runs)    */
+    uint32_t flags;           /* APO_FLAG_*                                       */
+    void *stream;             /* hipStream_t the library launches on, or NULL for a
+                                 stream the library creates and owns; an external
+                                 stream must outlive the handle                   */
+    void *workspace;          /* device buffer of >= apo_workspace_bytes bytes the
+                                 library uses for all its device state, or NULL to
+                                 let the library allocate it; an external buffer
+                                 must outlive the handle                          */
+    size_t workspace_bytes;   /* size of workspace when it is not NULL            */
+} apo_options;
+
+/* Device bytes apo_create needs for these sizes and options (0 if the
+ * arguments are invalid).  Nothing is allocated. */
+size_t apo_workspace_bytes(int32_t dim, int32_t pop, int32_t np, const apo_options *opt);
+
+/* Create an optimiser (Algorithm 1, input and initialisation).
+ *   dim     D >= 1 coordinates per protozoan
+ *   lb, ub  host [dim] bounds X_min < X_max, finite (copied)
+ *   pop     population size ps >= 2
+ *   np      neighbour pairs in Eqs. (6) and (8), 1 <= np <= 8
+ *   pf_max  maximum fraction in Eq. (11), 0 <= pf_max <= 1
+ *   seed    Philox key of every random draw
+ *   opt     options (required)
+ *   out     receives the handle
+ * Draws the initial population uniformly in the bounds and evaluates it
+ * (ps function evaluations).  Asynchronous on the handle's stream.
+ * Errors: APO_E_INVAL (bad argument), APO_E_UNSUPPORTED (sizes beyond
+ * dim <= 1024 for elementwise objectives, dim <= 256 (FP64) or 512 (FP32)
+ * for rotated ones, pop > 65536), APO_E_NOMEM, APO_E_DEVICE. */
+int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int32_t np,
+               double pf_max, uint64_t seed, const apo_options *opt, apo_t **out);
+
+/* One iteration t -> t + 1 of Algorithm 1's loop body: sort by fitness,
+ * draw pf and Dr, build every candidate (dormancy Eq. (1), reproduction
+ * Eqs. (2)-(3), autotroph Eqs. (4)-(7), heterotroph Eqs. (8)-(10)) from the
+ * population as it stood at the start of the iteration, clamp to the
+ * bounds, evaluate, and keep a candidate only if its fitness is strictly
+ * lower.  Asynchronous.  APO_E_DONE once t == max_iter. */
+int apo_step(apo_t *h);
+
+/* Up to iters more iterations (clipped to max_iter - t), launched as a
+ * replayed HIP graph.  Returns the number executed (>= 0) or a status. */
+int apo_run(apo_t *h, int32_t iters);
+
+/* The best protozoan (lowest fitness; NaN never wins; lowest id on ties):
+ * x_out host [dim], f_out host scalar, fes_out host scalar = function
+ * evaluations so far = pop * (t + 1).  Any output may be NULL.
+ * Synchronises the handle's stream. */
+int apo_best(apo_t *h, double *x_out, double *f_out, int64_t *fes_out);
+
+/* Completed iterations t and function evaluations (either may be NULL). */
+int apo_info(const apo_t *h, int32_t *iter, int64_t *fes);
+
+/* Release every resource of the handle (external stream and workspace are
+ * left alone).  NULL is accepted. */
+int apo_destroy(apo_t *h);
+
+/* Checkpoint: copy out X host [pop][dim], F host [pop] and t.  Any output
+ * may be NULL.  Synchronises. */
+int apo_get_state(apo_t *h, double *X, double *F, int32_t *iter);
+
+/* Resume / inject: replace X (host [pop][dim], rounded to the handle's
+ * precision), F (host [pop], same) and t (0 <= t <= max_iter).  Values are
+ * taken as given (F is not recomputed).  Synchronises. */
+int apo_set_state(apo_t *h, const double *X, const double *F, int32_t iter);
+
+/* Record of the last apo_step (handles created with APO_FLAG_TRACE only,
+ * else APO_E_STATE): Y host [pop][dim] clamped candidates by id, Fy host
+ * [pop] their fitness, op host [pop] operation by id (0 dormancy,
+ * 1 reproduction, 2 autotroph, 3 heterotroph), perm host [pop] id of each
+ * rank (rank 0 best).  Any output may be NULL.  Synchronises. */
+int apo_get_trace(apo_t *h, double *Y, double *Fy, int32_t *op, int32_t *perm);
+
+/* Per-kernel timing of n more iterations (n >= 1, clipped like apo_run),
+ * measured with HIP events on the handle's stream around each launch:
+ * avg_us[0] rank sort, avg_us[1] step (update + evaluation + selection).
+ * Returns the number of iterations executed or a status. */
+int apo_time_kernels(apo_t *h, int32_t n, double *avg_us);
+
+/* 256-bin grey-level histogram of an 8-bit image (the input of the Kapur and
+ * Otsu objectives): d_img device [n] bytes, d_hist device [256] uint32
+ * counts (overwritten), stream a hipStream_t or NULL (null stream).
+ * n < 2^32.  Asynchronous.  APO_E_INVAL for NULL pointers. */
+int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint32_t *d_hist, void *stream);
+
+/* Static description of a status code. */
+const char *apo_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APO_H */

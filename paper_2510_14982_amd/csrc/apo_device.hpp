@@ -1,0 +1,197 @@
+// apo_device.hpp -- device-side primitives of the APO step for gfx950:
+// the counter-based draw stream, the keyed subset permutation behind
+// "randperm", the fitness order used by the rank sort, and wavefront
+// reductions.  Header-only, included by the kernels only.
+#pragma once
+
+#ifndef APO_HOST_SHIM   // defined only by the CPU test harness of these primitives
+#include <hip/hip_runtime.h>
+#endif
+#include <stdint.h>
+
+namespace apok {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Ten rounds of two
+// 32x32 -> 64-bit products; the key advances by the Weyl constants between
+// rounds.  The counter is (purpose << 24 | block, index, iteration, run) and
+// the key is the 64-bit seed.
+// ---------------------------------------------------------------------------
+struct Words {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Words r;
+    r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
+    return r;
+}
+
+enum : uint32_t { TAG_INIT = 1, TAG_ITER = 2, TAG_RANK = 3, TAG_ELEM = 4 };
+
+struct Stream {
+    uint32_t k0, k1, run;
+    __device__ __forceinline__ Words block(uint32_t tag, uint32_t blk, uint32_t index,
+                                           uint32_t iter) const {
+        return philox4x32_10((tag << 24) | blk, index, iter, run, k0, k1);
+    }
+};
+
+// "rand" in (0, 1): (k + 1/2) 2^-23 with k the top 23 bits of the word.  The
+// value has 24 significant bits, so binary32 and binary64 hold it exactly.
+template <typename T>
+__device__ __forceinline__ T uniform(uint32_t w) {
+    return (T(w >> 9) + T(0.5)) * T(1.1920928955078125e-07);  // 2^-23
+}
+
+// Uniform integer in [0, n): floor(w n / 2^32).
+__device__ __forceinline__ uint32_t bounded(uint32_t w, uint32_t n) {
+    return __umulhi(w, n);
+}
+
+// ---------------------------------------------------------------------------
+// Keyed bijection of [0, n): alternating Feistel network over
+// b = max(2, ceil(log2 n)) bits, cycle-walked back into [0, n).  The
+// element x belongs to the m-subset iff pi(x) < m, which gives exactly m
+// members with O(1) work per element and no shared state, so every lane
+// decides its own coordinates.  Round counts grow as the domain shrinks
+// (24, 20, 16, 12, 8 for b <= 4, 5-6, 7, 8-9, >= 10); for b <= 6 the round
+// function is a table held in the round key, above it is the top bits of
+// a 24 x 24-bit product.  Round keys 8.. are derived from keys 0..7.
+// ---------------------------------------------------------------------------
+struct Subset {
+    uint32_t k[24];
+    uint32_t n;        // domain size
+    uint32_t rounds;   // even
+    uint32_t a0, c0;   // initial widths of the left / right halves
+    uint32_t walk;     // 2^b: no cycle of the pass is longer
+    bool table;
+};
+
+__device__ __forceinline__ void subset_init(Subset &s, const uint32_t *keys8, uint32_t n) {
+    uint32_t bits = 2;
+    while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
+    s.n = n;
+    s.rounds = bits <= 4 ? 24u : bits <= 6 ? 20u : bits <= 7 ? 16u : bits <= 9 ? 12u : 8u;
+    s.table = bits <= 6;
+    s.a0 = bits - bits / 2;
+    s.c0 = bits / 2;
+    s.walk = bits >= 32 ? 0xFFFFFFFFu : (1u << bits);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s.k[i] = keys8[i];
+#pragma unroll
+    for (int i = 8; i < 24; ++i) {
+        uint32_t x = s.k[i - 8] ^ (s.k[i - 7] >> 16) ^ (uint32_t)i;
+        x = x * 0x7FEB352Du;
+        s.k[i] = x ^ (x >> 15);
+    }
+}
+
+__device__ __forceinline__ uint32_t subset_pass(const Subset &s, uint32_t x) {
+    const uint32_t a0 = s.a0, c0 = s.c0;
+    uint32_t L = x >> c0;
+    uint32_t R = x & ((1u << c0) - 1u);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+        if ((uint32_t)i < s.rounds) {
+            const uint32_t a = (i & 1) ? c0 : a0;   // current left width
+            const uint32_t c = (i & 1) ? a0 : c0;   // current right width
+            uint32_t f;
+            if (s.table)
+                f = (s.k[i] >> (a * R)) & ((1u << a) - 1u);
+            else   // HIP's __umul24 returns int: shift the product as unsigned
+                f = (uint32_t)__umul24((R << (24u - c)) ^ (s.k[i] >> 8),
+                                       (s.k[i] & 0xFFFFFFu) | 1u) >>
+                    (32u - a);
+            const uint32_t nl = R;
+            R = L ^ f;
+            L = nl;
+        }
+    }
+    return (L << c0) | R;   // an even number of rounds restores the widths
+}
+
+// Cycle walking: the pass permutes [0, 2^b), so the orbit of x < n comes
+// back below n within 2^b passes; the count bounds the loop regardless.
+__device__ __forceinline__ uint32_t subset_pi(const Subset &s, uint32_t x) {
+    uint32_t y = x;
+    uint32_t steps = 0;
+    do {
+        y = subset_pass(s, y);
+    } while (y >= s.n && ++steps < s.walk);
+    return y;
+}
+
+// Membership in the m-subset; m >= n selects all, m == 0 none.
+__device__ __forceinline__ bool subset_has(const Subset &s, uint32_t x, uint32_t m) {
+    if (m >= s.n) return true;
+    if (m == 0) return false;
+    return subset_pi(s, x) < m;
+}
+
+// Membership bits of the four elements x0 .. x0+3 (bit e for x0 + e); the
+// loop is kept rolled so the Feistel rounds are emitted once.
+__device__ __forceinline__ uint32_t subset_bits4(const Subset &s, uint32_t x0, uint32_t m) {
+    if (m >= s.n) return 0xFu;
+    if (m == 0) return 0u;
+    uint32_t bits = 0;
+#pragma unroll 1
+    for (uint32_t e = 0; e < 4; ++e) {
+        const uint32_t x = x0 + e;
+        if (x < s.n && subset_pi(s, x) < m) bits |= 1u << e;
+    }
+    return bits;
+}
+
+// ---------------------------------------------------------------------------
+// Fitness order: ascending, -0 == +0, every NaN after +inf, ties by id.
+// The order-preserving unsigned image of a float/double; NaN maps to the
+// all-ones pattern, both zeros to the image of +0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t order_key(float f) {
+    if (f != f) return 0xFFFFFFFFu;
+    if (f == 0.0f) f = 0.0f;
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t order_key(double f) {
+    if (f != f) return 0xFFFFFFFFFFFFFFFFull;
+    if (f == 0.0) f = 0.0;
+    const uint64_t b = (uint64_t)__double_as_longlong(f);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Strict "better than" used by the greedy selection: NaN never wins.
+template <typename T>
+__device__ __forceinline__ bool strictly_less(T a, T b) {
+    return a < b;
+}
+
+// Butterfly sum over an aligned group of G lanes.  Each stage adds the same
+// two operands in every lane of a pair, so all lanes of the group end with
+// bit-identical totals.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int s = 1; s < G; s <<= 1) v += __shfl_xor(v, s, 64);
+    return v;
+}
+
+}  // namespace apok

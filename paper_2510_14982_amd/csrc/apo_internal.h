@@ -1,0 +1,69 @@
+// apo_internal.h -- state shared between the host runtime (apo_api.cpp) and
+// the kernel launchers (apo_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apok {
+
+enum : int32_t { OP_DORMANCY = 0, OP_REPRODUCTION = 1, OP_AUTOTROPH = 2, OP_HETEROTROPH = 3 };
+enum : int32_t { K_SPHERE = 0, K_RASTRIGIN = 1, K_ROSENBROCK = 2, K_ACKLEY = 3, K_KAPUR = 4,
+                 K_OTSU = 5 };
+
+constexpr int kMaxNp = 8;        // neighbour pairs supported
+constexpr int kTileRanks = 16;   // ranks per workgroup in the tiled step (one MFMA row block)
+
+// Device-resident control block, one per handle.  The rank kernel opens
+// iteration t_next = t + 1 and draws its scalars; the step kernel closes it.
+struct Ctrl {
+    int32_t t;            // completed iterations
+    int32_t t_next;       // iteration being computed
+    int32_t m_dr;         // |Dr| of iteration t_next
+    int32_t best_id;      // written by the best kernel
+    uint32_t dr_keys[8];  // subset keys of Dr for iteration t_next
+    double best_f;
+    int32_t pad[48];
+};
+
+// Everything a kernel needs, passed by value.  Element pointers are typed
+// by the handle's precision (float or double).
+struct Params {
+    int32_t dim, pop, np, max_iter;
+    int32_t Dp;           // row stride (elements) of X and Y
+    int32_t kind;         // objective
+    int32_t rotated;      // 1: z = M (x - o) through the packed matrix
+    int32_t Nt, Ks;       // MFMA tiles: output column tiles of 16, k-steps of 4
+    int32_t trace;        // 1: write candidates to the trace buffers
+    uint32_t seed_lo, seed_hi, run;
+    double pf_max;
+    void *X[2];           // [pop][Dp] positions, indexed by t & 1
+    void *F[2];           // [pop] fitness, indexed by t & 1
+    int32_t *perm;        // [pop] rank -> id
+    Ctrl *ctrl;
+    const double *p_ah;   // [max_iter + 1] Eq. (12)
+    const double *fscale; // [max_iter + 1] 1 + cos(pi t / T) of Eq. (4)
+    const double *cnear;  // [max_iter + 1] 1 - t / T of Eq. (9)
+    const double *p_dr;   // [pop] Eq. (13) for rank r + 1
+    const void *lb, *ub, *shift;   // [Dp]
+    const void *rotp;     // packed MFMA B fragments of M^T
+    const double *htab;   // histogram prefix tables (4 x 257)
+    void *trY;            // [pop][Dp]
+    void *trF;            // [pop]
+    int32_t *trOp;        // [pop]
+};
+
+// Launchers (apo_kernels.hip).  All asynchronous on `s`; they return the
+// launch status.
+hipError_t launch_init(const Params &p, bool fp64, hipStream_t s);
+hipError_t launch_rank(const Params &p, bool fp64, hipStream_t s);
+hipError_t launch_step(const Params &p, bool fp64, hipStream_t s);
+hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s);
+hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream_t s);
+hipError_t launch_histogram(const uint8_t *img, uint64_t n, uint32_t *hist, hipStream_t s);
+
+// Lanes per protozoan and 4-element chunks per lane used for a dimension.
+int lanes_for_dim(int dim);
+int chunks_for_dim(int dim);
+
+}  // namespace apok

@@ -1,0 +1,617 @@
+// apo_step.hpp -- the fused step kernels (candidate construction, clamp,
+// objective, greedy selection) as templates.  Instantiated per precision
+// and kernel family in apo_step_*.hip so the builds run in parallel.
+#pragma once
+#include <math.h>
+
+#include "apo_device.hpp"
+#include "apo_internal.h"
+
+namespace apok {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kE = 2.71828182845904523536;
+constexpr double kEps = 2.220446049250313e-16;   // 2^-52, the eps of Eqs. (7), (10)
+
+template <typename T>
+struct V4;
+template <>
+struct V4<float> {
+    typedef float __attribute__((ext_vector_type(4))) type;
+};
+template <>
+struct V4<double> {
+    typedef double __attribute__((ext_vector_type(4))) type;
+};
+
+template <typename T>
+__device__ __forceinline__ void load4(const T *p, T v[4]) {
+    const typename V4<T>::type q = *reinterpret_cast<const typename V4<T>::type *>(p);
+    v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T *p, const T v[4]) {
+    typename V4<T>::type q;
+    q[0] = v[0]; q[1] = v[1]; q[2] = v[2]; q[3] = v[3];
+    *reinterpret_cast<typename V4<T>::type *>(p) = q;
+}
+
+// cos(2 pi z): binary64 follows the textbook expression; binary32 uses
+// cospi(2z), whose argument is exact.
+__device__ __forceinline__ double cos2pi(double z) { return cos(2.0 * kPi * z); }
+__device__ __forceinline__ float cos2pi(float z) { return cospif(2.0f * z); }
+
+__device__ __forceinline__ Stream stream_of(const Params &p) {
+    Stream s;
+    s.k0 = p.seed_lo;
+    s.k1 = p.seed_hi;
+    s.run = p.run;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Per-protozoan plan of one iteration: which operation, its mask, scalars
+// and neighbours.  Every lane of the protozoan's group computes the same
+// plan (the group shares a wavefront, so this costs no extra issue slots).
+// ---------------------------------------------------------------------------
+template <typename T, int NPMAX>
+struct Plan {
+    int32_t op, id, r;
+    uint32_t m;        // mask size: ceil(D i / ps) (Eq. (5)), ceil(D rand) (Eq. (3)), D
+    Subset mask;
+    T fac;             // f of Eq. (4)
+    T srep;            // +-rand of Eq. (2)
+    T sgn;             // +- of Eq. (9)
+    T cn;              // 1 - iter / iter_max of Eq. (9)
+    T fold;            // fitness of the row
+    int32_t idj;       // X_j of Eq. (6)
+    int32_t idm[NPMAX], idp[NPMAX];   // (k-, k+) of Eq. (6) or (i-k, i+k) of Eq. (8)
+    T w[NPMAX];        // Eq. (7) / Eq. (10)
+};
+
+template <typename T>
+__device__ __forceinline__ T weight(T fa, T fb) {
+    return exp(-fabs(fa / (fb + T(kEps))));
+}
+
+template <typename T, int NPMAX>
+__device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T *F,
+                                          Plan<T, NPMAX> &c) {
+    const Stream rng = stream_of(p);
+    const int ps = p.pop, D = p.dim;
+    c.r = r;
+    c.id = p.perm[r];
+    c.fold = F[c.id];
+    c.fac = T(0); c.srep = T(0); c.sgn = T(1); c.cn = T(p.cnear[t]); c.idj = 0;
+    const Words s0 = rng.block(TAG_RANK, 0, (uint32_t)r, (uint32_t)t);
+    const Words k1 = rng.block(TAG_RANK, 1, (uint32_t)r, (uint32_t)t);
+    const Words k2 = rng.block(TAG_RANK, 2, (uint32_t)r, (uint32_t)t);
+    const uint32_t keys[8] = {k1.w[0], k1.w[1], k1.w[2], k1.w[3],
+                              k2.w[0], k2.w[1], k2.w[2], k2.w[3]};
+    subset_init(c.mask, keys, (uint32_t)D);
+    const double u_op = uniform<double>(s0.w[0]);
+    const double u_f = uniform<double>(s0.w[1]);
+    const double u_rep = uniform<double>(s0.w[2]);
+    const double sgn = uniform<double>(s0.w[3]) < 0.5 ? 1.0 : -1.0;
+    c.sgn = T(sgn);
+
+    bool in_dr;
+    {
+        Subset drs;
+        uint32_t dk[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dk[i] = p.ctrl->dr_keys[i];
+        subset_init(drs, dk, (uint32_t)ps);
+        in_dr = subset_has(drs, (uint32_t)r, (uint32_t)p.ctrl->m_dr);
+    }
+    const Words q3 = rng.block(TAG_RANK, 3, (uint32_t)r, (uint32_t)t);
+    if (in_dr) {
+        if (p.p_dr[r] > u_op) {                       // Eq. (13) -> dormancy
+            c.op = OP_DORMANCY;
+            c.m = (uint32_t)D;
+        } else {                                      // reproduction, |M_r| = ceil(D rand)
+            c.op = OP_REPRODUCTION;
+            const uint64_t k = q3.w[0] >> 9;
+            c.m = (uint32_t)(((uint64_t)D * (2ull * k + 1ull) + (1ull << 24) - 1ull) >> 24);
+            c.srep = T(sgn * u_rep);
+        }
+    } else {
+        c.fac = T(u_f * p.fscale[t]);
+        c.m = (uint32_t)(((uint64_t)D * (uint64_t)(r + 1) + (uint64_t)ps - 1ull) / (uint64_t)ps);
+        if (p.p_ah[t] > u_op) {                       // Eq. (12) -> autotroph
+            c.op = OP_AUTOTROPH;
+            c.idj = p.perm[bounded(q3.w[1], (uint32_t)ps)];
+#pragma unroll
+            for (int k = 0; k < NPMAX; ++k) {
+                if (k < p.np) {
+                    // words 2k+2 (k-) and 2k+3 (k+) of the sequence starting at block 3
+                    uint32_t wm, wp;
+                    if (k == 0) {
+                        wm = q3.w[2];
+                        wp = q3.w[3];
+                    } else {
+                        const Words b = rng.block(TAG_RANK, 3 + (uint32_t)(2 * k + 2) / 4,
+                                                  (uint32_t)r, (uint32_t)t);
+                        wm = b.w[(2 * k + 2) & 3];
+                        wp = b.w[(2 * k + 3) & 3];
+                    }
+                    const int km = r == 0 ? r : (int)bounded(wm, (uint32_t)r);
+                    const int kp = r == ps - 1 ? r : r + 1 + (int)bounded(wp, (uint32_t)(ps - 1 - r));
+                    c.idm[k] = p.perm[km];
+                    c.idp[k] = p.perm[kp];
+                    c.w[k] = weight<T>(F[c.idm[k]], F[c.idp[k]]);
+                } else {
+                    c.idm[k] = c.idp[k] = 0;
+                    c.w[k] = T(0);
+                }
+            }
+        } else {                                      // heterotroph
+            c.op = OP_HETEROTROPH;
+#pragma unroll
+            for (int k = 0; k < NPMAX; ++k) {
+                if (k < p.np) {
+                    const int a = r - (k + 1) < 0 ? 0 : r - (k + 1);
+                    const int b = r + (k + 1) > ps - 1 ? ps - 1 : r + (k + 1);
+                    c.idm[k] = p.perm[a];
+                    c.idp[k] = p.perm[b];
+                    c.w[k] = weight<T>(F[c.idm[k]], F[c.idp[k]]);
+                } else {
+                    c.idm[k] = c.idp[k] = 0;
+                    c.w[k] = T(0);
+                }
+            }
+        }
+    }
+}
+
+// Candidate values of the four coordinates d0..d0+3 of one protozoan,
+// clamped to the bounds.  x receives the row's own values.  Coordinates at
+// or beyond D are set to zero (the row padding).
+template <typename T, int NPMAX>
+__device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX> &c, int t,
+                                           bool init, int d0, const T *Xc, T x[4], T y[4]) {
+    const int D = p.dim, Dp = p.Dp;
+    T lb[4], ub[4];
+    load4((const T *)p.lb + d0, lb);
+    load4((const T *)p.ub + d0, ub);
+    if (init) {
+        x[0] = x[1] = x[2] = x[3] = T(0);
+    } else {
+        load4(Xc + (size_t)c.id * Dp + d0, x);
+    }
+    const Stream rng = stream_of(p);
+    T U[4] = {T(0), T(0), T(0), T(0)};
+    if (init) {
+        const Words u = rng.block(TAG_INIT, (uint32_t)(d0 >> 2), (uint32_t)c.id, 0u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) U[e] = uniform<T>(u.w[e]);
+    } else if (c.op != OP_AUTOTROPH) {
+        const Words u = rng.block(TAG_ELEM, (uint32_t)(d0 >> 2), (uint32_t)c.r, (uint32_t)t);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) U[e] = uniform<T>(u.w[e]);
+    }
+    const uint32_t mb = (init || c.op == OP_DORMANCY) ? 0xFu : subset_bits4(c.mask, (uint32_t)d0, c.m);
+    if (init || c.op == OP_DORMANCY) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[e] = lb[e] + U[e] * (ub[e] - lb[e]);   // Eq. (1)
+    } else if (c.op == OP_REPRODUCTION) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            y[e] = x[e];
+            if ((mb >> e) & 1u)
+                y[e] = x[e] + c.srep * (lb[e] + U[e] * (ub[e] - lb[e]));        // Eq. (2)
+        }
+    } else {
+        T acc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < NPMAX; ++k) {
+            if (k < p.np) {
+                T xm[4], xp[4];
+                load4(Xc + (size_t)c.idm[k] * Dp + d0, xm);
+                load4(Xc + (size_t)c.idp[k] * Dp + d0, xp);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[e] = acc[e] + c.w[k] * (xm[e] - xp[e]);
+            }
+        }
+        const T npd = T(p.np);
+        if (c.op == OP_AUTOTROPH) {
+            T xj[4];
+            load4(Xc + (size_t)c.idj * Dp + d0, xj);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                y[e] = x[e];
+                if ((mb >> e) & 1u)
+                    y[e] = x[e] + c.fac * ((xj[e] - x[e]) + acc[e] / npd);          // Eq. (6)
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                y[e] = x[e];
+                if ((mb >> e) & 1u) {
+                    const T xnear = (T(1) + (c.sgn * U[e]) * c.cn) * x[e];         // Eq. (9)
+                    y[e] = x[e] + c.fac * ((xnear - x[e]) + acc[e] / npd);          // Eq. (8)
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        y[e] = (d0 + e < D) ? fmin(fmax(y[e], lb[e]), ub[e]) : T(0);
+        if (d0 + e >= D) x[e] = T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused elementwise step.  G lanes per protozoan (a power of two <= 64, so a
+// group never straddles a wavefront), NCH chunks of 4 coordinates per lane.
+// ---------------------------------------------------------------------------
+template <typename T, int G, int NCH, int NPMAX>
+__global__ __launch_bounds__(256) void step_elem(Params p, int init) {
+    const int lane = threadIdx.x & (G - 1);
+    const int item = (blockIdx.x * 256 + threadIdx.x) / G;
+    if (item >= p.pop) return;
+    const int D = p.dim, Dp = p.Dp;
+    const int t = init ? 0 : p.ctrl->t_next;
+    const int src = (t + 1) & 1, dst = t & 1;
+    const T *Xc = (const T *)p.X[src];
+    const T *Fc = (const T *)p.F[src];
+    T *Xn = (T *)p.X[dst];
+    T *Fn = (T *)p.F[dst];
+
+    Plan<T, NPMAX> c;
+    if (init) {
+        c.op = OP_DORMANCY; c.id = item; c.r = item; c.m = (uint32_t)D; c.fold = T(0);
+    } else {
+        make_plan<T, NPMAX>(p, item, t, Fc, c);
+    }
+
+    T xs[NCH][4], ys[NCH][4];
+    const T *o = (const T *)p.shift;
+    T s1 = T(0), s2 = T(0);
+    T zfirst[NCH], zs[NCH][4];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int d0 = 4 * (lane + ch * G);
+        if (d0 < D) {
+            candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, xs[ch], ys[ch]);
+            T ov[4];
+            load4(o + d0, ov);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) zs[ch][e] = ys[ch][e] - ov[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xs[ch][e] = ys[ch][e] = zs[ch][e] = T(0);
+        }
+        zfirst[ch] = zs[ch][0];
+    }
+    // objective
+    if (p.kind == K_ROSENBROCK) {
+        const int wl = threadIdx.x & 63;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            // next coordinate after this lane's chunk: lane + 1, or lane 0 of the next chunk
+            const T nb_same = __shfl(zfirst[ch], wl + 1 < 64 ? wl + 1 : wl, 64);
+            const T nb_next = __shfl(zfirst[ch + 1 < NCH ? ch + 1 : ch], wl - (G - 1), 64);
+            const T after = lane < G - 1 ? nb_same : nb_next;
+            const int d0 = 4 * (lane + ch * G);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (d0 + e + 1 < D) {
+                    const T a = zs[ch][e] + T(1);
+                    const T b = (e < 3 ? zs[ch][e + 1] : after) + T(1);
+                    s1 += T(100) * (b - a * a) * (b - a * a) + (a - T(1)) * (a - T(1));
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int d0 = 4 * (lane + ch * G);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (d0 + e < D) {
+                    const T z = zs[ch][e];
+                    if (p.kind == K_RASTRIGIN) {
+                        s1 += z * z - T(10) * cos2pi(z) + T(10);
+                    } else {
+                        s1 += z * z;
+                        if (p.kind == K_ACKLEY) s2 += cos2pi(z);
+                    }
+                }
+            }
+        }
+    }
+    s1 = group_sum<G>(s1);
+    T fnew;
+    if (p.kind == K_ACKLEY) {
+        s2 = group_sum<G>(s2);
+        fnew = T(-20) * exp(T(-0.2) * sqrt(s1 / T(D))) - exp(s2 / T(D)) + T(20) + T(kE);
+    } else {
+        fnew = s1;
+    }
+    const bool accept = init || strictly_less(fnew, c.fold);
+    T *row = Xn + (size_t)c.id * Dp;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int d0 = 4 * (lane + ch * G);
+        if (d0 < D) store4(row + d0, accept ? ys[ch] : xs[ch]);
+    }
+    if (lane == 0) Fn[c.id] = accept ? fnew : c.fold;
+    if (!init && blockIdx.x == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
+    if (p.trace && !init) {
+        T *ty = (T *)p.trY + (size_t)c.id * Dp;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int d0 = 4 * (lane + ch * G);
+            if (d0 < D) store4(ty + d0, ys[ch]);
+        }
+        if (lane == 0) {
+            ((T *)p.trF)[c.id] = fnew;
+            p.trOp[c.id] = c.op;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled step: 16 protozoa per workgroup of 512 threads.
+// LDS: Ys[16][LS] candidates, Xs[16][LS] own rows, Zs[16][LZ] transformed
+// coordinates (rotated objectives) or sorted thresholds (histogram ones).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16 x 16 output held by element v of lane l (column l % 16).
+// The f32 form keeps four consecutive rows per lane group (row 4 (l/16) + v);
+// the f64 form interleaves them (row 4 v + l/16), as measured on gfx950.
+template <typename T>
+__device__ __forceinline__ int mfma_out_row(int l, int v);
+template <>
+__device__ __forceinline__ int mfma_out_row<float>(int l, int v) { return 4 * (l >> 4) + v; }
+template <>
+__device__ __forceinline__ int mfma_out_row<double>(int l, int v) { return 4 * v + (l >> 4); }
+
+template <typename T>
+__device__ __forceinline__ double threshold_objective(const Params &p, const T *yrow, int *ts) {
+    const int k = p.dim;
+    for (int c = 0; c < k; ++c) {
+        // round half to even, then insertion into the sorted prefix
+        int v = (int)rint((double)yrow[c]);
+        int j = c;
+        while (j > 0 && ts[j - 1] > v) {
+            ts[j] = ts[j - 1];
+            --j;
+        }
+        ts[j] = v;
+    }
+    const double *P = p.htab, *S = p.htab + 257, *M1 = p.htab + 514;
+    double total = 0.0;
+    int a = 0;
+    if (p.kind == K_KAPUR) {
+        for (int c = 0; c <= k; ++c) {
+            const int b = c < k ? ts[c] : 256;
+            const double omega = P[b] - P[a];
+            if (omega > 0.0) total += log(omega) - (S[b] - S[a]) / omega;
+            a = b;
+        }
+        return -total;
+    }
+    const double muT = M1[256];
+    for (int c = 0; c <= k; ++c) {
+        const int b = c < k ? ts[c] : 256;
+        const double omega = P[b] - P[a];
+        if (omega > 0.0) {
+            const double mu = (M1[b] - M1[a]) / omega;
+            total += omega * (mu - muT) * (mu - muT);
+        }
+        a = b;
+    }
+    return -total;
+}
+
+template <typename T, int G, int NCH, int NPMAX>
+__global__ __launch_bounds__(512) void step_tile(Params p, int init) {
+    constexpr int NT = 512, TM = kTileRanks, GROUPS = NT / G;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t s_id[TM], s_op[TM];
+    __shared__ T s_fold[TM], s_fnew[TM];
+    const int D = p.dim, Dp = p.Dp;
+    const int LS = Dp + 1, LZ = p.Nt * 16 + 1;
+    T *Ys = (T *)smem;
+    T *Xs = Ys + TM * LS;
+    T *Zs = Xs + TM * LS;
+    const int t = init ? 0 : p.ctrl->t_next;
+    const int src = (t + 1) & 1, dst = t & 1;
+    const T *Xc = (const T *)p.X[src];
+    const T *Fc = (const T *)p.F[src];
+    T *Xn = (T *)p.X[dst];
+    T *Fn = (T *)p.F[dst];
+    const T *o = (const T *)p.shift;
+    const int r0 = blockIdx.x * TM;
+    const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
+
+    // phase 1: candidates into LDS
+    for (int row = grp; row < TM; row += GROUPS) {
+        const int item = r0 + row;
+        if (item < p.pop) {
+            Plan<T, NPMAX> c;
+            if (init) {
+                c.op = OP_DORMANCY; c.id = item; c.r = item; c.m = (uint32_t)D; c.fold = T(0);
+            } else {
+                make_plan<T, NPMAX>(p, item, t, Fc, c);
+            }
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int d0 = 4 * (lane + ch * G);
+                if (d0 < D) {
+                    T x[4], y[4];
+                    candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, x, y);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (d0 + e < D) {
+                            Ys[row * LS + d0 + e] = y[e];
+                            Xs[row * LS + d0 + e] = x[e];
+                        }
+                    }
+                }
+            }
+            if (lane == 0) {
+                s_id[row] = c.id;
+                s_op[row] = c.op;
+                s_fold[row] = c.fold;
+            }
+        } else {
+            for (int d = lane; d < D; d += G) Ys[row * LS + d] = Xs[row * LS + d] = T(0);
+            if (lane == 0) s_id[row] = -1;
+        }
+    }
+    __syncthreads();
+
+    const bool thresholds = p.kind == K_KAPUR || p.kind == K_OTSU;
+    if (p.rotated) {
+        // phase 2: Z = (Y - o) M^T on the matrix cores.  Fragment layout of
+        // v_mfma 16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
+        // the output row of (lane, element) is given by mfma_out_row.
+        const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const typename V4<T>::type zero = {T(0), T(0), T(0), T(0)};
+        const T *B = (const T *)p.rotp;
+        for (int nt = wave; nt < p.Nt; nt += NT / 64) {
+            typename V4<T>::type acc = zero;
+            for (int ks = 0; ks < p.Ks; ++ks) {
+                const int k = 4 * ks + (l >> 4);
+                const int i = l & 15;
+                const T a = k < D ? Ys[i * LS + k] - o[k] : T(0);
+                const T b = B[((size_t)ks * p.Nt + nt) * 64 + l];
+                acc = mfma16x16x4(a, b, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Zs[mfma_out_row<T>(l, v) * LZ + 16 * nt + (l & 15)] = acc[v];
+        }
+        __syncthreads();
+    }
+
+    // phase 3: objective per protozoan
+    if (thresholds) {
+        if (threadIdx.x < TM && s_id[threadIdx.x] >= 0) {
+            int *ts = (int *)Zs + threadIdx.x * (D + 1);
+            s_fnew[threadIdx.x] = T(threshold_objective<T>(p, Ys + threadIdx.x * LS, ts));
+        }
+    } else {
+        for (int row = grp; row < TM; row += GROUPS) {
+            T s1 = T(0), s2 = T(0);
+            if (s_id[row] >= 0) {
+                for (int d = lane; d < D; d += G) {
+                    const T z = p.rotated ? Zs[row * LZ + d] : Ys[row * LS + d] - o[d];
+                    if (p.kind == K_ROSENBROCK) {
+                        if (d + 1 < D) {
+                            const T zn = p.rotated ? Zs[row * LZ + d + 1] : Ys[row * LS + d + 1] - o[d + 1];
+                            const T a = z + T(1), b = zn + T(1);
+                            s1 += T(100) * (b - a * a) * (b - a * a) + (a - T(1)) * (a - T(1));
+                        }
+                    } else if (p.kind == K_RASTRIGIN) {
+                        s1 += z * z - T(10) * cos2pi(z) + T(10);
+                    } else {
+                        s1 += z * z;
+                        if (p.kind == K_ACKLEY) s2 += cos2pi(z);
+                    }
+                }
+            }
+            s1 = group_sum<G>(s1);
+            s2 = group_sum<G>(s2);
+            if (lane == 0 && s_id[row] >= 0) {
+                s_fnew[row] = p.kind == K_ACKLEY
+                                  ? T(-20) * exp(T(-0.2) * sqrt(s1 / T(D))) - exp(s2 / T(D)) +
+                                        T(20) + T(kE)
+                                  : s1;
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase 4: greedy selection and the double-buffered write
+    if (!init && blockIdx.x == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
+    for (int row = grp; row < TM; row += GROUPS) {
+        const int id = s_id[row];
+        if (id < 0) continue;
+        const T fnew = s_fnew[row];
+        const bool accept = init || strictly_less(fnew, s_fold[row]);
+        const T *srcrow = accept ? Ys + row * LS : Xs + row * LS;
+        T *out = Xn + (size_t)id * Dp;
+        for (int d = lane; d < D; d += G) out[d] = srcrow[d];
+        if (lane == 0) Fn[id] = accept ? fnew : s_fold[row];
+        if (p.trace && !init) {
+            T *ty = (T *)p.trY + (size_t)id * Dp;
+            for (int d = lane; d < D; d += G) ty[d] = Ys[row * LS + d];
+            if (lane == 0) {
+                ((T *)p.trF)[id] = fnew;
+                p.trOp[id] = s_op[row];
+            }
+        }
+    }
+}
+
+
+inline bool use_tile(const Params &p) {
+    return p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
+}
+
+inline size_t tile_lds_bytes(const Params &p, bool fp64) {
+    const size_t es = fp64 ? 8 : 4;
+    const size_t LS = (size_t)p.Dp + 1, LZ = (size_t)p.Nt * 16 + 1;
+    size_t z = kTileRanks * LZ * es;
+    const size_t ts = kTileRanks * ((size_t)p.dim + 1) * sizeof(int);
+    if (ts > z) z = ts;
+    return 2 * kTileRanks * LS * es + z;
+}
+
+template <typename T, int NPMAX>
+hipError_t launch_tile_t(const Params &p, int init, hipStream_t s) {
+    const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
+    if (NCH < 0) return hipErrorInvalidValue;
+    {
+        const dim3 grid((p.pop + kTileRanks - 1) / kTileRanks), block(512);
+        const size_t lds = tile_lds_bytes(p, sizeof(T) == 8);
+#define APO_TILE(GG, CC)                                                                     \
+    if (G == GG && NCH == CC) {                                                              \
+        if (lds > 65536) {                                                                   \
+            const hipError_t ea = hipFuncSetAttribute(                                       \
+                (const void *)step_tile<T, GG, CC, NPMAX>,                                   \
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                       \
+            if (ea != hipSuccess) return ea;                                                 \
+        }                                                                                    \
+        hipLaunchKernelGGL((step_tile<T, GG, CC, NPMAX>), grid, block, lds, s, p, init);     \
+        return hipGetLastError();                                                            \
+    }
+        APO_TILE(4, 1) APO_TILE(8, 1) APO_TILE(16, 1) APO_TILE(32, 1) APO_TILE(64, 1)
+        APO_TILE(64, 2)
+#undef APO_TILE
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int NPMAX>
+hipError_t launch_elem_t(const Params &p, int init, hipStream_t s) {
+    const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
+    if (NCH < 0) return hipErrorInvalidValue;
+    const long long threads = (long long)p.pop * G;
+    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+#define APO_ELEM(GG, CC)                                                                     \
+    if (G == GG && NCH == CC) {                                                              \
+        hipLaunchKernelGGL((step_elem<T, GG, CC, NPMAX>), grid, block, 0, s, p, init);       \
+        return hipGetLastError();                                                            \
+    }
+    APO_ELEM(4, 1) APO_ELEM(8, 1) APO_ELEM(16, 1) APO_ELEM(32, 1) APO_ELEM(64, 1)
+    APO_ELEM(64, 2) APO_ELEM(64, 4)
+#undef APO_ELEM
+    return hipErrorInvalidValue;
+}
+
+
+}  // namespace apok

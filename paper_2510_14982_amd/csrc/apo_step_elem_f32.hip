@@ -1,0 +1,10 @@
+// apo_step_elem_f32.hip -- fused elementwise step kernels, binary32.
+#include "apo_step.hpp"
+
+namespace apok {
+
+hipError_t launch_elem_f32(const Params &p, int init, hipStream_t s) {
+    return p.np == 1 ? launch_elem_t<float, 1>(p, init, s) : launch_elem_t<float, kMaxNp>(p, init, s);
+}
+
+}  // namespace apok

@@ -1,0 +1,10 @@
+// apo_step_elem_f64.hip -- fused elementwise step kernels, binary64.
+#include "apo_step.hpp"
+
+namespace apok {
+
+hipError_t launch_elem_f64(const Params &p, int init, hipStream_t s) {
+    return p.np == 1 ? launch_elem_t<double, 1>(p, init, s) : launch_elem_t<double, kMaxNp>(p, init, s);
+}
+
+}  // namespace apok

@@ -1,0 +1,106 @@
+"""The C-ABI library loads, exports every function include/apo.h declares,
+and its host-side argument checks reject bad input without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "apo.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b(apo_[a-z0-9_]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2510_14982_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libapo.so is not built (run __graft_entry__.build())")
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("apo_create", "apo_step", "apo_run", "apo_best", "apo_destroy",
+                 "apo_get_state", "apo_set_state", "apo_histogram_u8", "apo_strerror"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_workspace_sizes(L):
+    from paper_2510_14982_amd import _lib
+    for rc in (0, -1, -2, -3, -4, -5, -6):
+        assert len(_lib.strerror(rc)) > 3
+    o = _lib.Options()
+    o.max_iter = 10
+    o.precision = _lib.APO_FP32
+    n1 = L.apo_workspace_bytes(100, 4096, 1, C.byref(o))
+    assert n1 >= 2 * 4096 * 112 * 4
+    o.flags = _lib.APO_FLAG_TRACE
+    assert L.apo_workspace_bytes(100, 4096, 1, C.byref(o)) > n1
+    assert L.apo_workspace_bytes(0, 4096, 1, C.byref(o)) == 0
+    assert L.apo_workspace_bytes(10, 1, 1, C.byref(o)) == 0
+
+
+def _create(L, dim=3, lb=None, ub=None, pop=8, np_pairs=1, pf_max=0.1, max_iter=10,
+            precision=0, kind=0, hist=None, shift=None, rot=None):
+    from paper_2510_14982_amd import _lib
+    lb = np.full(dim, -1.0) if lb is None else np.asarray(lb, np.float64)
+    ub = np.full(dim, 1.0) if ub is None else np.asarray(ub, np.float64)
+    o = _lib.Options()
+    o.max_iter = max_iter
+    o.precision = precision
+    o.objective.kind = kind
+    if hist is not None:
+        hist = np.ascontiguousarray(hist, np.uint64)
+        o.objective.hist = hist.ctypes.data_as(C.POINTER(C.c_uint64))
+    if shift is not None:
+        o.objective.shift = _lib._dptr(np.ascontiguousarray(shift, np.float64))
+    if rot is not None:
+        rot = np.ascontiguousarray(rot, np.float64)
+        o.objective.rot = _lib._dptr(rot)
+    h = C.c_void_p()
+    return L.apo_create(dim, _lib._dptr(lb), _lib._dptr(ub), pop, np_pairs, pf_max, 1,
+                        C.byref(o), C.byref(h))
+
+
+def test_create_rejects_bad_arguments_on_the_host(L):
+    INVAL, UNSUP = -1, -6
+    assert _create(L, dim=0) == INVAL
+    assert _create(L, pop=1) == INVAL
+    assert _create(L, np_pairs=0) == INVAL
+    assert _create(L, np_pairs=9) == INVAL
+    assert _create(L, pf_max=1.5) == INVAL
+    assert _create(L, pf_max=float("nan")) == INVAL
+    assert _create(L, max_iter=0) == INVAL
+    assert _create(L, precision=7) == INVAL
+    assert _create(L, kind=9) == INVAL
+    assert _create(L, lb=[0, 0, 1], ub=[1, 1, 1]) == INVAL            # lb == ub
+    assert _create(L, lb=[0, 0, float("inf")], ub=[1, 1, 2]) == INVAL
+    assert _create(L, shift=[0, float("nan"), 0]) == INVAL
+    assert _create(L, kind=4) == INVAL                                 # Kapur without histogram
+    assert _create(L, kind=4, hist=np.zeros(256)) == INVAL             # empty histogram
+    assert _create(L, kind=4, hist=np.ones(256), lb=[-1, 0, 0], ub=[255, 255, 255]) == INVAL
+    assert _create(L, kind=4, hist=np.ones(256), lb=[0, 0, 0], ub=[255, 256, 255]) == INVAL
+    assert _create(L, pop=65537) == UNSUP
+    assert _create(L, dim=2000, lb=np.zeros(2000), ub=np.ones(2000)) == UNSUP
+    assert _create(L, dim=600, lb=np.zeros(600), ub=np.ones(600), rot=np.eye(600)) == UNSUP
+
+
+def test_null_handles_and_histogram_arguments(L):
+    assert L.apo_step(None) == -1
+    assert L.apo_run(None, 3) == -1
+    assert L.apo_destroy(None) == 0
+    assert L.apo_histogram_u8(None, 10, None, None) == -1

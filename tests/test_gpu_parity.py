@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path against the oracle, element by element, from
+identical injected state, through the C ABI (every case prints its name
+before it touches the GPU)."""
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+from gpu_common import compare_step, make_pair, need_gpu, random_state
+
+pytestmark = pytest.mark.gpu
+
+STEP_CASES = [
+    # name, kwargs, iteration t, max_iter
+    ("c1_shape_rastrigin_fp64", dict(dim=10, pop=32, kind="rastrigin"), 1, 200),
+    ("worked_example_shape_sphere", dict(dim=3, pop=4, kind="sphere", lb=0.0, ub=10.0), 1, 50),
+    ("ragged_rosenbrock_np2", dict(dim=37, pop=50, kind="rosenbrock", np_pairs=2), 7, 40),
+    ("ackley_g64", dict(dim=130, pop=64, kind="ackley", pf_max=0.5), 3, 30),
+    ("rastrigin_two_chunks", dict(dim=300, pop=40, kind="rastrigin", pf_max=1.0), 2, 10),
+    ("sphere_four_chunks_np3", dict(dim=1000, pop=24, kind="sphere", np_pairs=3), 5, 9),
+    ("last_iteration", dict(dim=16, pop=33, kind="rastrigin", pf_max=0.3), 20, 20),
+    ("no_dr", dict(dim=8, pop=17, kind="sphere", pf_max=0.0), 4, 10),
+    ("all_dr", dict(dim=8, pop=17, kind="sphere", pf_max=1.0), 4, 10),
+    ("pop2_dim1", dict(dim=1, pop=2, kind="rastrigin"), 1, 3),
+    ("rotated_rastrigin_fp64", dict(dim=20, pop=70, kind="rastrigin", rotated=True), 3, 50),
+    ("rotated_rosenbrock_np3_fp64", dict(dim=33, pop=40, kind="rosenbrock", rotated=True,
+                                         np_pairs=3), 2, 20),
+    ("elem_rastrigin_fp32", dict(dim=100, pop=300, kind="rastrigin", precision="fp32"), 5, 100),
+    ("rotated_rastrigin_fp32", dict(dim=100, pop=300, kind="rastrigin", rotated=True,
+                                    precision="fp32"), 5, 100),
+    ("rotated_ackley_fp32", dict(dim=50, pop=100, kind="ackley", rotated=True,
+                                 precision="fp32", pf_max=0.4), 9, 20),
+    ("rotated_sphere_fp32_d200", dict(dim=200, pop=48, kind="sphere", rotated=True,
+                                      precision="fp32"), 2, 10),
+]
+
+
+@pytest.mark.parametrize("name,kw,t,T", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_step_parity(name, kw, t, T):
+    apo = need_gpu()
+    print(f"[parity] {name} t={t} T={T} {kw}", flush=True)
+    prec = kw.get("precision", "fp64")
+    g, p = make_pair(apo, max_iter=T, seed=11, **kw)
+    with g:
+        for rep, sseed in enumerate((3, 4)):
+            X, F = random_state(p, sseed, prec)
+            compare_step(g, p, t, X, F, prec)
+
+
+@pytest.mark.parametrize("k", [1, 4, 8, 16])
+@pytest.mark.parametrize("kind", ["kapur", "otsu"])
+def test_threshold_step_parity(kind, k):
+    apo = need_gpu()
+    print(f"[parity] {kind} k={k}", flush=True)
+    img = gen.blob_image(256, 256, seed=5)
+    hist = gen.histogram_of(img)
+    g, p = make_pair(apo, dim=k, pop=130, kind=kind, precision="fp32", lb=0.0, ub=255.0,
+                     hist=hist, max_iter=50, seed=2)
+    with g:
+        X, F = random_state(p, 9, "fp32")
+        compare_step(g, p, 4, X, F, "fp32")
+
+
+@pytest.mark.parametrize("precision,rotated,dim", [("fp64", False, 10), ("fp64", True, 24),
+                                                   ("fp32", False, 100), ("fp32", True, 100)])
+def test_initial_population(precision, rotated, dim):
+    apo = need_gpu()
+    print(f"[init] {precision} rotated={rotated} dim={dim}", flush=True)
+    g, p = make_pair(apo, dim=dim, pop=77, kind="rastrigin", precision=precision,
+                     rotated=rotated, max_iter=5, seed=21)
+    with g:
+        X, F, t = g.get_state()
+        Xo, Fo = p.init()
+        assert t == 0
+        if precision == "fp64":
+            assert np.array_equal(X, Xo)
+            assert np.allclose(F, Fo, rtol=1e-12, atol=0)
+        else:
+            assert np.allclose(X, Xo, rtol=1e-6, atol=1e-5)
+            assert np.allclose(F, Fo, rtol=1e-5, atol=1e-4)
+
+
+def test_c1_full_run_matches_oracle():
+    """ps 32, D 10, 200 FP64 iterations of shifted Rastrigin from the GPU's
+    own initialisation: the whole trajectory is reproduced (no near ties
+    occur on this seed), checked every 25 iterations."""
+    apo = need_gpu()
+    print("[run] c1 full trajectory", flush=True)
+    w = gen.shifted_rastrigin_small(seed=1)
+    with apo.APO(w.dim, w.lb, w.ub, w.pop, seed=w.seed, max_iter=w.max_iter, precision="fp64",
+                 kind=w.kind, shift=w.shift) as g:
+        p = O.Problem(dim=w.dim, pop=w.pop, lb=w.lb, ub=w.ub, max_iter=w.max_iter, seed=w.seed,
+                      kind=w.kind, shift=w.shift)
+        Xo, Fo = p.init()
+        t = 0
+        while t < w.max_iter:
+            n = g.run(25)
+            Xo, Fo, t2 = p.run(Xo, Fo, t, n)
+            t += n
+            X, F, tg = g.get_state()
+            assert tg == t == t2
+            assert np.allclose(X, Xo, rtol=1e-9, atol=1e-9), t
+            assert np.allclose(F, Fo, rtol=1e-9, atol=1e-9), t
+        xb, fb, fes = g.best()
+        assert fes == w.pop * (w.max_iter + 1)
+        b = O.best(Fo)
+        assert abs(fb - Fo[b]) <= 1e-9 * max(1.0, abs(Fo[b]))
+
+
+def test_graph_replay_equals_single_steps_and_is_deterministic():
+    apo = need_gpu()
+    print("[run] graph replay vs steps", flush=True)
+    kw = dict(dim=100, pop=500, kind="rastrigin", rotated=True, precision="fp32", max_iter=40)
+    g1, _ = make_pair(apo, seed=5, **kw)
+    g2, _ = make_pair(apo, seed=5, **kw)
+    g3, _ = make_pair(apo, seed=5, **kw)
+    with g1, g2, g3:
+        assert g1.run(40) == 40
+        for _ in range(40):
+            assert g2.step()
+        assert not g2.step()
+        g3.run(13)
+        g3.run(100)
+        a, b, c = g1.get_state(), g2.get_state(), g3.get_state()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+        assert a[2] == b[2] == c[2] == 40
+
+
+def test_checkpoint_resume_bit_identical():
+    apo = need_gpu()
+    print("[run] checkpoint resume", flush=True)
+    kw = dict(dim=30, pop=64, kind="ackley", precision="fp32", max_iter=30)
+    g1, _ = make_pair(apo, seed=8, **kw)
+    g2, _ = make_pair(apo, seed=8, **kw)
+    with g1, g2:
+        g1.run(30)
+        g2.run(11)
+        X, F, t = g2.get_state()
+        g2.set_state(X, F, t)
+        g2.run(30)
+        assert np.array_equal(g1.get_state()[0], g2.get_state()[0])
+        assert np.array_equal(g1.get_state()[1], g2.get_state()[1])
+
+
+def test_best_order_ties_and_nan():
+    apo = need_gpu()
+    print("[best] ties and NaN", flush=True)
+    g, p = make_pair(apo, dim=5, pop=9, kind="sphere", max_iter=3)
+    with g:
+        X = gen.random_state(9, 5, p.lb, p.ub, 1)
+        F = np.array([3.0, np.nan, 1.0, -0.0, 0.0, 1.0, np.nan, 7.0, 0.0])
+        g.set_state(X, F, 0)
+        x, f, fes = g.best()
+        assert f == 0.0 and np.array_equal(x, X[3])        # -0 == +0, lowest id
+        F2 = np.full(9, np.nan)
+        F2[6] = 5.0
+        g.set_state(X, F2, 1)
+        x, f, fes = g.best()
+        assert f == 5.0 and np.array_equal(x, X[6]) and fes == 9 * 2
+
+
+def test_bounds_monotone_best_and_done():
+    apo = need_gpu()
+    print("[run] invariants", flush=True)
+    g, p = make_pair(apo, dim=64, pop=256, kind="rastrigin", rotated=True, precision="fp32",
+                     max_iter=60, pf_max=0.5)
+    with g:
+        last = np.inf
+        for k in range(6):
+            g.run(10)
+            X, F, t = g.get_state()
+            assert np.all(X >= p.lb) and np.all(X <= p.ub)
+            assert F.min() <= last
+            last = F.min()
+        assert not g.step()
+        assert g.run(5) == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4096 * 3 + 5])
+@pytest.mark.parametrize("offset", [0, 3])
+def test_histogram_bit_exact(n, offset):
+    apo = need_gpu()
+    import torch
+    print(f"[hist] n={n} offset={offset}", flush=True)
+    rng = np.random.default_rng(n + offset)
+    host = rng.integers(0, 256, size=n + offset, dtype=np.uint8)
+    dev = torch.from_numpy(host).cuda()
+    h = apo.histogram_u8(dev[offset:]).cpu().numpy().astype(np.int64)
+    assert np.array_equal(h, np.bincount(host[offset:], minlength=256))
+
+
+def test_histogram_blob_image_full_size():
+    apo = need_gpu()
+    import torch
+    print("[hist] blob 4096x4096", flush=True)
+    img = gen.blob_image(4096, 4096, seed=1)
+    h = apo.histogram_u8(torch.from_numpy(img).cuda().reshape(-1)).cpu().numpy()
+    assert np.array_equal(h.astype(np.int64), np.bincount(img.reshape(-1), minlength=256))
+    for const in (0, 255):
+        im = torch.full((1 << 20,), const, dtype=torch.uint8, device="cuda")
+        hc = apo.histogram_u8(im).cpu().numpy()
+        assert hc[const] == 1 << 20 and hc.sum() == 1 << 20
