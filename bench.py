@@ -56,7 +56,7 @@ def cpu_baseline(w, budget_s: float):
     import oracle as O
     p = O.Problem(dim=w.dim, pop=w.pop, lb=w.lb, ub=w.ub, np_pairs=w.np_pairs,
                   max_iter=w.max_iter, pf_max=w.pf_max, seed=w.seed, kind=w.kind,
-                  shift=w.shift, rot=w.rot)
+                  shift=w.shift, rot=w.rot, hist=w.hist)
     X, F = p.init()
     t0 = time.perf_counter()
     n = 0
@@ -67,16 +67,70 @@ def cpu_baseline(w, budget_s: float):
             break
     dt = time.perf_counter() - t0
     return {"value": w.pop * n / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"iterations 1..{n} of the {w.pop}x{w.dim} rotated-Rastrigin FP32 "
-                      f"workload, evaluated by the single-threaded FP64 oracle ({dt:.1f} s)"}
+            "sample": f"iterations 1..{n} of {w.name} (from the oracle's own initial "
+                      f"population), single-threaded FP64 oracle, {dt:.1f} s"}
+
+
+def make_handle(apo, w, precision):
+    return apo.APO(w.dim, w.lb, w.ub, w.pop, np_pairs=w.np_pairs, pf_max=w.pf_max,
+                   seed=w.seed, max_iter=w.max_iter, precision=precision, kind=w.kind,
+                   shift=w.shift, rot=w.rot, hist=w.hist)
+
+
+def timed_run(torch, apo, w, precision, steps, warmup):
+    """Warm-up on one handle, then `steps` iterations on fresh handles (runs
+    of the configured length chained if steps exceeds one run)."""
+    with make_handle(apo, w, precision) as g:
+        g.run(max(1, min(warmup, w.max_iter)))
+        g.best()
+    torch.cuda.synchronize()
+    remaining = steps
+    handles = []
+    while remaining > 0:
+        handles.append((make_handle(apo, w, precision), min(remaining, w.max_iter)))
+        remaining -= w.max_iter
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h, n in handles:
+        h.run(n)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    best_f = handles[-1][0].best()[1]
+    for h, _ in handles:
+        h.close()
+    return dt, best_f
+
+
+def kernel_times(apo, w, precision, iters):
+    with make_handle(apo, w, precision) as g:
+        n, kt = g.time_kernels(min(iters, w.max_iter))
+    return n, kt
+
+
+def workload(name, seed):
+    import gen
+    if name == "c2":
+        return gen.rotated_rastrigin_large(seed=seed), "fp32"
+    if name == "c1":
+        return gen.shifted_rastrigin_small(seed=seed), "fp64"
+    if name == "c3":
+        return gen.kapur_thresholds(k=16, seed=seed), "fp32"
+    if name == "elem-large":
+        w = gen.rotated_rastrigin_large(seed=seed, pop=8192, dim=1000, max_iter=200)
+        w.rot = None
+        w.name = "shifted_rastrigin_ps8192_d1000_fp32"
+        return w, "fp32"
+    raise SystemExit(f"unknown workload {name}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed iterations (default: the workload's configured run length)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "elem-large"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
@@ -89,7 +143,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import gen
     import paper_2510_14982_amd as apo
 
     if args.copy_calibration:
@@ -102,75 +155,70 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": 5}))
         return
 
-    w = gen.rotated_rastrigin_large(seed=args.seed)
-
-    def handle():
-        return apo.APO(w.dim, w.lb, w.ub, w.pop, np_pairs=w.np_pairs, pf_max=w.pf_max,
-                       seed=w.seed, max_iter=w.max_iter, precision="fp32", kind=w.kind,
-                       shift=w.shift, rot=w.rot)
-
-    # warm-up: graph capture, code-object load, clocks
-    with handle() as g:
-        g.run(max(1, min(args.warmup, w.max_iter)))
-        g.best()
-    torch.cuda.synchronize()
-
-    # timed region: K iterations, fresh runs of the configured length chained
-    # when K exceeds one run
-    remaining = args.steps
-    handles = []
-    while remaining > 0:
-        h = handle()
-        handles.append((h, min(remaining, w.max_iter)))
-        remaining -= w.max_iter
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for h, n in handles:
-        h.run(n)
-    for h, _ in handles:
-        h.info()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    _, best_f, fes = handles[-1][0].best()
-    for h, _ in handles:
-        h.close()
-
-    # per-kernel durations with HIP events on the handle's stream
-    with handle() as g:
-        kn, kt = g.time_kernels(min(args.kernel_iters, w.max_iter))
+    w, precision = workload(args.workload, args.seed)
+    steps = w.max_iter if args.steps is None else args.steps
+    es = 8 if precision == "fp64" else 4
+    extra = {}
+    if args.workload == "c3":
+        # the image is reduced once on the GPU; time that kernel on its own
+        img = torch.from_numpy(w.extra["image"]).cuda().reshape(-1)
+        apo.histogram_u8(img)
+        torch.cuda.synchronize()
+        reps = 20
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            h = apo.histogram_u8(img)
+        ev1.record()
+        torch.cuda.synchronize()
+        hist_us = ev0.elapsed_time(ev1) * 1000.0 / reps
+        got = h.cpu().numpy().astype("uint64")
+        assert (got == w.hist).all(), "GPU histogram differs from numpy's"
+        extra["histogram"] = {"pixels": int(img.numel()), "us": hist_us,
+                              "GB_per_s": img.numel() / (hist_us * 1e-6) / 1e9,
+                              "hbm_frac": img.numel() / (hist_us * 1e-6) / 1e9 / PEAK_HBM_GBS}
+    dt, best_f = timed_run(torch, apo, w, precision, steps, args.warmup)
+    kn, kt = kernel_times(apo, w, precision, args.kernel_iters)
     step_us = kt["step_us"]
-    flops = 2.0 * w.pop * w.dim * w.dim            # z = M (y - o) for every candidate
-    bytes_alg = 2.0 * w.pop * w.dim * 4            # read X once, write X' once (binary32)
-    achieved = flops / (step_us * 1e-6) / 1e12
-    traffic = measured_traffic()
-
+    bytes_alg = 2.0 * w.pop * w.dim * es          # read X once, write X' once
     out = {
         "metric": "fitness evals/sec + APO iters/sec at pop x D; %HBM roofline / %MFMA peak",
-        "value": w.pop * args.steps / dt,
+        "value": w.pop * steps / dt,
         "unit": "evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": 1000.0 * dt / args.steps,
+        "ms_per_step": 1000.0 * dt / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "pop": w.pop, "dim": w.dim, "iterations": w.max_iter,
-                   "np": w.np_pairs, "pf_max": w.pf_max, "objective": "shifted-rotated rastrigin",
-                   "parallelism": "single GPU"},
-        "iters_per_s": args.steps / dt,
+                   "np": w.np_pairs, "pf_max": w.pf_max, "objective": w.kind,
+                   "rotated": w.rot is not None, "parallelism": "single GPU"},
+        "iters_per_s": steps / dt,
         "final_best_f": best_f,
         "kernel_us": {"rank_sort": kt["rank_us"], "step": step_us, "iterations": kn},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": traffic,
-                     "kernel": "step_tile<float> (update + clamp + z = M(y-o) on MFMA + select)",
-                     "algorithmic_flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": bytes_alg,
-                     "hbm_frac_at_algorithmic_bytes": bytes_alg / (step_us * 1e-6) / 1e9 / PEAK_HBM_GBS},
     }
+    out.update(extra)
+    if w.rot is not None:
+        flops = 2.0 * w.pop * w.dim * w.dim        # z = M (y - o) for every candidate
+        achieved = flops / (step_us * 1e-6) / 1e12
+        out["roofline"] = {
+            "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+            "traffic": measured_traffic() if args.workload == "c2" else None,
+            "kernel": "step_tile<float> (update + clamp + z = M(y-o) on MFMA + select)",
+            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_alg,
+            "hbm_frac_at_algorithmic_bytes": bytes_alg / (step_us * 1e-6) / 1e9 / PEAK_HBM_GBS}
+    else:
+        achieved = bytes_alg / (step_us * 1e-6) / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "kernel": "step (update + clamp + objective + select)",
+            "algorithmic_bytes_per_launch": bytes_alg}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -25,10 +25,11 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_
                                                uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32 x 32 -> 64-bit product each (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -84,7 +85,8 @@ struct Subset {
     bool table;
 };
 
-__device__ __forceinline__ void subset_init(Subset &s, const uint32_t *keys8, uint32_t n) {
+// Domain-dependent parameters (everything except the keys).
+__device__ __forceinline__ void subset_shape(Subset &s, uint32_t n) {
     uint32_t bits = 2;
     while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
     s.n = n;
@@ -93,6 +95,10 @@ __device__ __forceinline__ void subset_init(Subset &s, const uint32_t *keys8, ui
     s.a0 = bits - bits / 2;
     s.c0 = bits / 2;
     s.walk = bits >= 32 ? 0xFFFFFFFFu : (1u << bits);
+}
+
+__device__ __forceinline__ void subset_init(Subset &s, const uint32_t *keys8, uint32_t n) {
+    subset_shape(s, n);
 #pragma unroll
     for (int i = 0; i < 8; ++i) s.k[i] = keys8[i];
 #pragma unroll
@@ -103,28 +109,72 @@ __device__ __forceinline__ void subset_init(Subset &s, const uint32_t *keys8, ui
     }
 }
 
-__device__ __forceinline__ uint32_t subset_pass(const Subset &s, uint32_t x) {
-    const uint32_t a0 = s.a0, c0 = s.c0;
+// One round's function of the right half R (width c) into a bits.
+template <bool TABLE>
+__device__ __forceinline__ uint32_t feistel_f(uint32_t k, uint32_t R, uint32_t a, uint32_t c) {
+    if (TABLE) return (k >> (a * R)) & ((1u << a) - 1u);
+    // HIP's __umul24 returns int: shift the product as unsigned
+    return (uint32_t)__umul24((R << (24u - c)) ^ (k >> 8), (k & 0xFFFFFFu) | 1u) >> (32u - a);
+}
+
+// A pass with a compile-time round count and round function, so the rounds
+// unroll without per-round branches.
+template <int ROUNDS, bool TABLE>
+__device__ __forceinline__ uint32_t feistel_fwd(const uint32_t *k, uint32_t a0, uint32_t c0,
+                                                uint32_t x) {
     uint32_t L = x >> c0;
     uint32_t R = x & ((1u << c0) - 1u);
 #pragma unroll
-    for (int i = 0; i < 24; ++i) {
-        if ((uint32_t)i < s.rounds) {
-            const uint32_t a = (i & 1) ? c0 : a0;   // current left width
-            const uint32_t c = (i & 1) ? a0 : c0;   // current right width
-            uint32_t f;
-            if (s.table)
-                f = (s.k[i] >> (a * R)) & ((1u << a) - 1u);
-            else   // HIP's __umul24 returns int: shift the product as unsigned
-                f = (uint32_t)__umul24((R << (24u - c)) ^ (s.k[i] >> 8),
-                                       (s.k[i] & 0xFFFFFFu) | 1u) >>
-                    (32u - a);
-            const uint32_t nl = R;
-            R = L ^ f;
-            L = nl;
-        }
+    for (int i = 0; i < ROUNDS; ++i) {
+        const uint32_t a = (i & 1) ? c0 : a0;   // current left width
+        const uint32_t c = (i & 1) ? a0 : c0;   // current right width
+        const uint32_t f = feistel_f<TABLE>(k[i], R, a, c);
+        const uint32_t nl = R;
+        R = L ^ f;
+        L = nl;
     }
     return (L << c0) | R;   // an even number of rounds restores the widths
+}
+
+// Inverse pass: forward round i maps (L, R) of widths (a, c) to
+// (R, L ^ f_i(R)) of widths (c, a); given (L', R') after round i,
+// R = L' and L = R' ^ f_i(L').
+template <int ROUNDS, bool TABLE>
+__device__ __forceinline__ uint32_t feistel_inv(const uint32_t *k, uint32_t a0, uint32_t c0,
+                                                uint32_t y) {
+    uint32_t L = y >> c0;
+    uint32_t R = y & ((1u << c0) - 1u);
+#pragma unroll
+    for (int i = ROUNDS - 1; i >= 0; --i) {
+        const uint32_t a = (i & 1) ? c0 : a0;   // left width before forward round i
+        const uint32_t c = (i & 1) ? a0 : c0;   // right width before forward round i
+        const uint32_t f = feistel_f<TABLE>(k[i], L, a, c);
+        const uint32_t prevR = L;
+        L = R ^ f;
+        R = prevR;
+    }
+    return (L << c0) | R;
+}
+
+// Round counts: 24 and 20 use the table function, 16, 12 and 8 the product.
+__device__ __forceinline__ uint32_t subset_pass(const Subset &s, uint32_t x) {
+    switch (s.rounds) {
+    case 24: return feistel_fwd<24, true>(s.k, s.a0, s.c0, x);
+    case 20: return feistel_fwd<20, true>(s.k, s.a0, s.c0, x);
+    case 16: return feistel_fwd<16, false>(s.k, s.a0, s.c0, x);
+    case 12: return feistel_fwd<12, false>(s.k, s.a0, s.c0, x);
+    default: return feistel_fwd<8, false>(s.k, s.a0, s.c0, x);
+    }
+}
+
+__device__ __forceinline__ uint32_t subset_pass_inv(const Subset &s, uint32_t y) {
+    switch (s.rounds) {
+    case 24: return feistel_inv<24, true>(s.k, s.a0, s.c0, y);
+    case 20: return feistel_inv<20, true>(s.k, s.a0, s.c0, y);
+    case 16: return feistel_inv<16, false>(s.k, s.a0, s.c0, y);
+    case 12: return feistel_inv<12, false>(s.k, s.a0, s.c0, y);
+    default: return feistel_inv<8, false>(s.k, s.a0, s.c0, y);
+    }
 }
 
 // Cycle walking: the pass permutes [0, 2^b), so the orbit of x < n comes
@@ -138,25 +188,47 @@ __device__ __forceinline__ uint32_t subset_pi(const Subset &s, uint32_t x) {
     return y;
 }
 
+// pi^-1 on [0, n): cycle walking through the inverse pass.
+__device__ __forceinline__ uint32_t subset_pi_inv(const Subset &s, uint32_t y) {
+    uint32_t x = y;
+    uint32_t steps = 0;
+    do {
+        x = subset_pass_inv(s, x);
+    } while (x >= s.n && ++steps < s.walk);
+    return x;
+}
+
+// The m-subset {x : pi(x) < m} = {pi^-1(i) : i < m} as a bitmask in LDS,
+// built by the G lanes of one group (all in one wavefront, all active).
+// Only min(m, n - m) inverse evaluations are needed: for m > n / 2 the
+// complement {pi^-1(i) : i >= m} is cleared from an all-ones mask.
+template <int G>
+__device__ __forceinline__ void subset_mask_group(const Subset &s, uint32_t m, uint32_t *words,
+                                                  int nwords, int lane) {
+    const uint32_t n = s.n;
+    const bool comp = m > n - m;
+    const uint32_t cnt = comp ? n - m : m;
+    for (int w = lane; w < nwords; w += G) words[w] = comp ? 0xFFFFFFFFu : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t idx = (uint32_t)lane; idx < cnt; idx += G) {
+        const uint32_t y = subset_pi_inv(s, comp ? m + idx : idx);
+        if (comp)
+            atomicAnd(&words[y >> 5], ~(1u << (y & 31)));
+        else
+            atomicOr(&words[y >> 5], 1u << (y & 31));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Membership in the m-subset; m >= n selects all, m == 0 none.
 __device__ __forceinline__ bool subset_has(const Subset &s, uint32_t x, uint32_t m) {
     if (m >= s.n) return true;
     if (m == 0) return false;
     return subset_pi(s, x) < m;
-}
-
-// Membership bits of the four elements x0 .. x0+3 (bit e for x0 + e); the
-// loop is kept rolled so the Feistel rounds are emitted once.
-__device__ __forceinline__ uint32_t subset_bits4(const Subset &s, uint32_t x0, uint32_t m) {
-    if (m >= s.n) return 0xFu;
-    if (m == 0) return 0u;
-    uint32_t bits = 0;
-#pragma unroll 1
-    for (uint32_t e = 0; e < 4; ++e) {
-        const uint32_t x = x0 + e;
-        if (x < s.n && subset_pi(s, x) < m) bits |= 1u << e;
-    }
-    return bits;
 }
 
 // ---------------------------------------------------------------------------

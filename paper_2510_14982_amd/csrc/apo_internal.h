@@ -21,9 +21,10 @@ struct Ctrl {
     int32_t t_next;       // iteration being computed
     int32_t m_dr;         // |Dr| of iteration t_next
     int32_t best_id;      // written by the best kernel
-    uint32_t dr_keys[8];  // subset keys of Dr for iteration t_next
+    uint32_t dr_keys[24]; // subset key schedule of Dr for iteration t_next
     double best_f;
-    int32_t pad[48];
+    double p_ah, fscale, cnear;   // Eqs. (12), (4), (9) at t_next
+    int32_t pad[26];
 };
 
 // Everything a kernel needs, passed by value.  Element pointers are typed
@@ -40,6 +41,7 @@ struct Params {
     void *X[2];           // [pop][Dp] positions, indexed by t & 1
     void *F[2];           // [pop] fitness, indexed by t & 1
     int32_t *perm;        // [pop] rank -> id
+    void *Fs;             // [pop] fitness in rank order (written with perm)
     Ctrl *ctrl;
     const double *p_ah;   // [max_iter + 1] Eq. (12)
     const double *fscale; // [max_iter + 1] 1 + cos(pi t / T) of Eq. (4)
@@ -65,5 +67,6 @@ hipError_t launch_histogram(const uint8_t *img, uint64_t n, uint32_t *hist, hipS
 // Lanes per protozoan and 4-element chunks per lane used for a dimension.
 int lanes_for_dim(int dim);
 int chunks_for_dim(int dim);
+
 
 }  // namespace apok

@@ -13,21 +13,42 @@
 namespace apok {
 
 // ---------------------------------------------------------------------------
-// Rank sort.  grid = ceil(pop / 64) workgroups of 1024 threads; each
-// workgroup ranks 64 protozoa (one per lane) and its 16 wavefronts split
-// the comparisons over the population.
+// Rank sort.  rank(i) = #{j : (F_j, j) before (F_i, i)} in the fitness order,
+// so perm[rank(i)] = i.  One workgroup of 256 threads ranks 16 protozoa:
+// thread t owns protozoan i = 16 b + (t % 16) and the t / 16-th sixteenth of
+// every tile of order keys staged in LDS (read by broadcast); the sixteen
+// partial counts of each protozoan are added by shuffles and through LDS.
+// No workgroup depends on another.  Block 0 also opens the iteration: pf
+// (Eq. (11)), |Dr| and the Dr subset key schedule.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool key_before(uint64_t kj, int j, uint64_t ki, int i) {
-    return kj < ki || (kj == ki && j < i);
-}
+constexpr int kRankTile = 4096;   // keys staged in LDS at a time (32 KB)
+constexpr int kRankPer = 16;      // protozoa ranked per workgroup
 
 template <typename T>
-__global__ __launch_bounds__(1024) void rank_kernel(Params p) {
-    __shared__ int32_t cnt[16][64];
+struct RankKey;
+template <>
+struct RankKey<float> {   // 32-bit order key with the id below it: unique
+    __device__ static uint64_t make(float f, int j) {
+        return ((uint64_t)order_key(f) << 32) | (uint32_t)j;
+    }
+    __device__ static bool before(uint64_t kj, int, uint64_t ki, int) { return kj < ki; }
+};
+template <>
+struct RankKey<double> {  // 64-bit order key; equal keys fall back to the ids
+    __device__ static uint64_t make(double f, int) { return order_key(f); }
+    __device__ static bool before(uint64_t kj, int j, uint64_t ki, int i) {
+        return kj < ki || (kj == ki && j < i);
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void rank_kernel(Params p) {
+    __shared__ uint64_t keys[kRankTile];
+    __shared__ int32_t part[4][kRankPer];
     const int tcur = p.ctrl->t;
     const T *F = (const T *)p.F[tcur & 1];
     const int ps = p.pop;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int il = threadIdx.x & (kRankPer - 1), jg = threadIdx.x >> 4;   // jg in 0..15
 
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const Stream rng = stream_of(p);
@@ -37,37 +58,47 @@ __global__ __launch_bounds__(1024) void rank_kernel(Params p) {
         p.ctrl->m_dr = (int32_t)ceil((double)ps * pf);                    // |Dr|
         const Words b1 = rng.block(TAG_ITER, 1, 0, (uint32_t)t);
         const Words b2 = rng.block(TAG_ITER, 2, 0, (uint32_t)t);
+        const uint32_t k8[8] = {b1.w[0], b1.w[1], b1.w[2], b1.w[3],
+                                b2.w[0], b2.w[1], b2.w[2], b2.w[3]};
+        Subset drs;
+        subset_init(drs, k8, (uint32_t)ps);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            p.ctrl->dr_keys[i] = b1.w[i];
-            p.ctrl->dr_keys[4 + i] = b2.w[i];
-        }
+        for (int q = 0; q < 24; ++q) p.ctrl->dr_keys[q] = drs.k[q];
+        p.ctrl->p_ah = p.p_ah[t];
+        p.ctrl->fscale = p.fscale[t];
+        p.ctrl->cnear = p.cnear[t];
         p.ctrl->t_next = t;
     }
 
-    const int i = blockIdx.x * 64 + lane;
-    const uint64_t ki = i < ps ? (uint64_t)order_key(F[i]) : ~0ull;
+    const int i = blockIdx.x * kRankPer + il;
+    const uint64_t ki = i < ps ? RankKey<T>::make(F[i], i) : ~0ull;
     int32_t c = 0;
-    const int nblk = (ps + 63) / 64;
-    for (int b = wave; b < nblk; b += 16) {
-        const int jl = b * 64 + lane;
-        const uint64_t kl = jl < ps ? (uint64_t)order_key(F[jl]) : ~0ull;
-        const int jmax = ps - b * 64 < 64 ? ps - b * 64 : 64;
-        const uint32_t klo = (uint32_t)kl, khi = (uint32_t)(kl >> 32);
-        for (int s = 0; s < jmax; ++s) {
-            const uint32_t lo = __builtin_amdgcn_readlane(klo, s);
-            const uint32_t hi = __builtin_amdgcn_readlane(khi, s);
-            const uint64_t kj = ((uint64_t)hi << 32) | lo;
-            c += key_before(kj, b * 64 + s, ki, i) ? 1 : 0;
-        }
-    }
-    cnt[wave][lane] = c;
-    __syncthreads();
-    if (wave == 0 && i < ps) {
-        int32_t rank = 0;
+    for (int base = 0; base < ps; base += kRankTile) {
+        const int n = min(kRankTile, ps - base);
+        __syncthreads();
+        for (int q = threadIdx.x; q < n; q += 256) keys[q] = RankKey<T>::make(F[base + q], base + q);
+        __syncthreads();
+        const int per = (n + 15) / 16;
+        const int q0 = jg * per, q1 = min(n, q0 + per);
+        int q = q0;
+        for (; q + 8 <= q1; q += 8) {
 #pragma unroll
-        for (int w = 0; w < 16; ++w) rank += cnt[w][lane];
+            for (int u = 0; u < 8; ++u)
+                c += RankKey<T>::before(keys[q + u], base + q + u, ki, i) ? 1 : 0;
+        }
+        for (; q < q1; ++q) c += RankKey<T>::before(keys[q], base + q, ki, i) ? 1 : 0;
+    }
+    // sum the 16 partial counts of protozoan il: lanes il + 16 {0..3} of each
+    // wavefront, then the four wavefronts
+    c += __shfl_xor(c, 16, 64);
+    c += __shfl_xor(c, 32, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < kRankPer) part[wave][lane] = c;
+    __syncthreads();
+    if (threadIdx.x < kRankPer && i < ps) {
+        const int rank = part[0][il] + part[1][il] + part[2][il] + part[3][il];
         p.perm[rank] = i;
+        ((T *)p.Fs)[rank] = F[i];
     }
 }
 
@@ -206,7 +237,7 @@ hipError_t launch_step(const Params &p, bool fp64, hipStream_t s) {
 }
 
 hipError_t launch_rank(const Params &p, bool fp64, hipStream_t s) {
-    const dim3 grid((p.pop + 63) / 64), block(1024);
+    const dim3 grid((p.pop + kRankPer - 1) / kRankPer), block(256);
     if (fp64)
         hipLaunchKernelGGL(rank_kernel<double>, grid, block, 0, s, p);
     else

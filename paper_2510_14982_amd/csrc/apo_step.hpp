@@ -63,6 +63,7 @@ struct Plan {
     int32_t op, id, r;
     uint32_t m;        // mask size: ceil(D i / ps) (Eq. (5)), ceil(D rand) (Eq. (3)), D
     Subset mask;
+    const uint32_t *mw;   // the group's LDS bitmask of the mask (M_f or M_r)
     T fac;             // f of Eq. (4)
     T srep;            // +-rand of Eq. (2)
     T sgn;             // +- of Eq. (9)
@@ -78,18 +79,29 @@ __device__ __forceinline__ T weight(T fa, T fb) {
     return exp(-fabs(fa / (fb + T(kEps))));
 }
 
-template <typename T, int NPMAX>
+// `lane0` is the wavefront lane of the group's first lane; the group has at
+// least four lanes, and its lanes 0..3 each draw one of the rank's blocks
+// 0..3, which are then exchanged across the group.
+template <typename T, int NPMAX, int G>
 __device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T *F,
+                                          int lane0, int lane, uint32_t *mwords,
                                           Plan<T, NPMAX> &c) {
     const Stream rng = stream_of(p);
     const int ps = p.pop, D = p.dim;
+    const T *Fs = (const T *)p.Fs;   // fitness by rank, written by the sort
     c.r = r;
     c.id = p.perm[r];
-    c.fold = F[c.id];
-    c.fac = T(0); c.srep = T(0); c.sgn = T(1); c.cn = T(p.cnear[t]); c.idj = 0;
-    const Words s0 = rng.block(TAG_RANK, 0, (uint32_t)r, (uint32_t)t);
-    const Words k1 = rng.block(TAG_RANK, 1, (uint32_t)r, (uint32_t)t);
-    const Words k2 = rng.block(TAG_RANK, 2, (uint32_t)r, (uint32_t)t);
+    c.fold = Fs[r];
+    c.fac = T(0); c.srep = T(0); c.sgn = T(1); c.cn = T(p.ctrl->cnear); c.idj = 0;
+    const Words mine = rng.block(TAG_RANK, (uint32_t)(lane & 3), (uint32_t)r, (uint32_t)t);
+    Words s0, k1, k2, q3;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        s0.w[e] = __shfl(mine.w[e], lane0 + 0, 64);
+        k1.w[e] = __shfl(mine.w[e], lane0 + 1, 64);
+        k2.w[e] = __shfl(mine.w[e], lane0 + 2, 64);
+        q3.w[e] = __shfl(mine.w[e], lane0 + 3, 64);
+    }
     const uint32_t keys[8] = {k1.w[0], k1.w[1], k1.w[2], k1.w[3],
                               k2.w[0], k2.w[1], k2.w[2], k2.w[3]};
     subset_init(c.mask, keys, (uint32_t)D);
@@ -102,13 +114,11 @@ __device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T
     bool in_dr;
     {
         Subset drs;
-        uint32_t dk[8];
+        subset_shape(drs, (uint32_t)ps);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) dk[i] = p.ctrl->dr_keys[i];
-        subset_init(drs, dk, (uint32_t)ps);
+        for (int i = 0; i < 24; ++i) drs.k[i] = p.ctrl->dr_keys[i];
         in_dr = subset_has(drs, (uint32_t)r, (uint32_t)p.ctrl->m_dr);
     }
-    const Words q3 = rng.block(TAG_RANK, 3, (uint32_t)r, (uint32_t)t);
     if (in_dr) {
         if (p.p_dr[r] > u_op) {                       // Eq. (13) -> dormancy
             c.op = OP_DORMANCY;
@@ -120,9 +130,9 @@ __device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T
             c.srep = T(sgn * u_rep);
         }
     } else {
-        c.fac = T(u_f * p.fscale[t]);
+        c.fac = T(u_f * p.ctrl->fscale);
         c.m = (uint32_t)(((uint64_t)D * (uint64_t)(r + 1) + (uint64_t)ps - 1ull) / (uint64_t)ps);
-        if (p.p_ah[t] > u_op) {                       // Eq. (12) -> autotroph
+        if (p.ctrl->p_ah > u_op) {                    // Eq. (12) -> autotroph
             c.op = OP_AUTOTROPH;
             c.idj = p.perm[bounded(q3.w[1], (uint32_t)ps)];
 #pragma unroll
@@ -143,7 +153,7 @@ __device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T
                     const int kp = r == ps - 1 ? r : r + 1 + (int)bounded(wp, (uint32_t)(ps - 1 - r));
                     c.idm[k] = p.perm[km];
                     c.idp[k] = p.perm[kp];
-                    c.w[k] = weight<T>(F[c.idm[k]], F[c.idp[k]]);
+                    c.w[k] = weight<T>(Fs[km], Fs[kp]);
                 } else {
                     c.idm[k] = c.idp[k] = 0;
                     c.w[k] = T(0);
@@ -158,7 +168,7 @@ __device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T
                     const int b = r + (k + 1) > ps - 1 ? ps - 1 : r + (k + 1);
                     c.idm[k] = p.perm[a];
                     c.idp[k] = p.perm[b];
-                    c.w[k] = weight<T>(F[c.idm[k]], F[c.idp[k]]);
+                    c.w[k] = weight<T>(Fs[a], Fs[b]);
                 } else {
                     c.idm[k] = c.idp[k] = 0;
                     c.w[k] = T(0);
@@ -166,6 +176,9 @@ __device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T
             }
         }
     }
+    c.mw = mwords;
+    if (c.op != OP_DORMANCY)
+        subset_mask_group<G>(c.mask, c.m, mwords, (D + 31) / 32, lane);
 }
 
 // Candidate values of the four coordinates d0..d0+3 of one protozoan,
@@ -194,7 +207,7 @@ __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX>
 #pragma unroll
         for (int e = 0; e < 4; ++e) U[e] = uniform<T>(u.w[e]);
     }
-    const uint32_t mb = (init || c.op == OP_DORMANCY) ? 0xFu : subset_bits4(c.mask, (uint32_t)d0, c.m);
+    const uint32_t mb = (init || c.op == OP_DORMANCY) ? 0xFu : (c.mw[d0 >> 5] >> (d0 & 31)) & 0xFu;
     if (init || c.op == OP_DORMANCY) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) y[e] = lb[e] + U[e] * (ub[e] - lb[e]);   // Eq. (1)
@@ -262,11 +275,14 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     T *Xn = (T *)p.X[dst];
     T *Fn = (T *)p.F[dst];
 
+    constexpr int MW = (4 * G * NCH + 31) / 32;
+    __shared__ uint32_t mwords[256 / G][MW];
     Plan<T, NPMAX> c;
     if (init) {
         c.op = OP_DORMANCY; c.id = item; c.r = item; c.m = (uint32_t)D; c.fold = T(0);
     } else {
-        make_plan<T, NPMAX>(p, item, t, Fc, c);
+        make_plan<T, NPMAX, G>(p, item, t, Fc, (threadIdx.x & 63) & ~(G - 1), lane,
+                               mwords[threadIdx.x / G], c);
     }
 
     T xs[NCH][4], ys[NCH][4];
@@ -421,6 +437,7 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     constexpr int NT = 512, TM = kTileRanks, GROUPS = NT / G;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_id[TM], s_op[TM];
+    __shared__ uint32_t s_mwords[GROUPS][(4 * G * NCH + 31) / 32];
     __shared__ T s_fold[TM], s_fnew[TM];
     const int D = p.dim, Dp = p.Dp;
     const int LS = Dp + 1, LZ = p.Nt * 16 + 1;
@@ -437,6 +454,20 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     const int r0 = blockIdx.x * TM;
     const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
 
+    // The first column tile of each wavefront's B fragments (packed M^T) is
+    // requested before phase 1 so the loads overlap the candidate work.
+    constexpr int PRE = sizeof(T) == 4 ? 32 : 16;
+    T bpre[PRE];
+    {
+        const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const T *B = (const T *)p.rotp;
+#pragma unroll
+        for (int ks = 0; ks < PRE; ++ks)
+            bpre[ks] = (p.rotated && wave < p.Nt && ks < p.Ks)
+                           ? B[((size_t)ks * p.Nt + wave) * 64 + l]
+                           : T(0);
+    }
+
     // phase 1: candidates into LDS
     for (int row = grp; row < TM; row += GROUPS) {
         const int item = r0 + row;
@@ -445,7 +476,8 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
             if (init) {
                 c.op = OP_DORMANCY; c.id = item; c.r = item; c.m = (uint32_t)D; c.fold = T(0);
             } else {
-                make_plan<T, NPMAX>(p, item, t, Fc, c);
+                make_plan<T, NPMAX, G>(p, item, t, Fc, (threadIdx.x & 63) & ~(G - 1), lane,
+                                       s_mwords[grp], c);
             }
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
@@ -482,11 +514,24 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
         const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
         const typename V4<T>::type zero = {T(0), T(0), T(0), T(0)};
         const T *B = (const T *)p.rotp;
+        const int i = l & 15;
         for (int nt = wave; nt < p.Nt; nt += NT / 64) {
             typename V4<T>::type acc = zero;
-            for (int ks = 0; ks < p.Ks; ++ks) {
+            int ks0 = 0;
+            if (nt == wave) {   // fragments already in registers
+#pragma unroll
+                for (int ks = 0; ks < PRE; ++ks) {
+                    if (ks < p.Ks) {
+                        const int k = 4 * ks + (l >> 4);
+                        const T a = k < D ? Ys[i * LS + k] - o[k] : T(0);
+                        acc = mfma16x16x4(a, bpre[ks], acc);
+                    }
+                }
+                ks0 = PRE;
+            }
+#pragma unroll 8
+            for (int ks = ks0; ks < p.Ks; ++ks) {
                 const int k = 4 * ks + (l >> 4);
-                const int i = l & 15;
                 const T a = k < D ? Ys[i * LS + k] - o[k] : T(0);
                 const T b = B[((size_t)ks * p.Nt + nt) * 64 + l];
                 acc = mfma16x16x4(a, b, acc);

@@ -7,6 +7,8 @@
 //   mode "pi":     lines "n x k0..k7"    -> pi(x)
 //   mode "philox": lines "c0 c1 c2 c3 k0 k1" -> 4 words
 //   mode "key32":  lines "<hex bits of a float>" -> order key
+//   mode "mask":   lines "n m k0..k7"    -> the members of the m-subset built
+//                  from inverse evaluations, ascending, space separated
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -22,6 +24,13 @@ static inline unsigned int __umulhi(unsigned int a, unsigned int b) {
 static inline unsigned int __float_as_uint(float f) { unsigned int u; std::memcpy(&u, &f, 4); return u; }
 static inline long long __double_as_longlong(double f) { long long u; std::memcpy(&u, &f, 8); return u; }
 template <class T> static inline T __shfl_xor(T v, int, int) { return v; }
+// one "lane" runs the whole group loop on the host (G = 1)
+#define __builtin_amdgcn_fence(a, b) ((void)0)
+#define __builtin_amdgcn_wave_barrier() ((void)0)
+#define __ATOMIC_RELEASE 0
+#define __ATOMIC_ACQUIRE 0
+static inline unsigned atomicOr(unsigned *p, unsigned v) { unsigned o = *p; *p |= v; return o; }
+static inline unsigned atomicAnd(unsigned *p, unsigned v) { unsigned o = *p; *p &= v; return o; }
 #include "apo_device.hpp"
 
 int main(int argc, char **argv) {
@@ -40,6 +49,19 @@ int main(int argc, char **argv) {
         while (std::scanf("%u %u %u %u %u %u", &c[0], &c[1], &c[2], &c[3], &k[0], &k[1]) == 6) {
             apok::Words w = apok::philox4x32_10(c[0], c[1], c[2], c[3], k[0], k[1]);
             std::printf("%u %u %u %u\n", w.w[0], w.w[1], w.w[2], w.w[3]);
+        }
+    } else if (!std::strcmp(mode, "mask")) {
+        unsigned n, m, k[8];
+        static unsigned words[1 << 11];
+        while (std::scanf("%u %u %u %u %u %u %u %u %u %u", &n, &m, &k[0], &k[1], &k[2], &k[3],
+                          &k[4], &k[5], &k[6], &k[7]) == 10) {
+            apok::Subset s;
+            apok::subset_init(s, k, n);
+            const int nw = (int)((n + 31) / 32);
+            apok::subset_mask_group<1>(s, m, words, nw, 0);
+            for (unsigned x = 0; x < n; ++x)
+                if ((words[x >> 5] >> (x & 31)) & 1u) std::printf("%u ", x);
+            std::printf("\n");
         }
     } else if (!std::strcmp(mode, "key32")) {
         unsigned b;

@@ -48,6 +48,22 @@ def test_subset_pi_matches_oracle_for_every_element(harness):
     assert got == want
 
 
+def test_inverse_mask_equals_forward_subset(harness):
+    """The GPU builds each mask from min(m, n - m) inverse evaluations; the
+    set must be exactly the oracle's {x : pi(x) < m}."""
+    rng = np.random.default_rng(9)
+    lines, want = [], []
+    for n in list(range(1, 140)) + [255, 256, 1000, 1024]:
+        for m in sorted({0, 1, n // 3, n // 2, (n + 1) // 2, n - 1, n} - {-1}):
+            if m < 0:
+                continue
+            keys = rng.integers(0, 2**32, size=8, dtype=np.uint64)
+            lines.append(f"{n} {m} " + " ".join(str(int(k)) for k in keys))
+            want.append([x for x in range(n) if O.subset_pi(x, n, keys) < m])
+    got = [[int(v) for v in l.split()] for l in _run(harness, "mask", lines)[:len(lines)]]
+    assert got == want
+
+
 def test_philox_matches_oracle(harness):
     rng = np.random.default_rng(8)
     q = rng.integers(0, 2**32, size=(200, 6), dtype=np.uint64)

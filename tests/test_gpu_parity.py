@@ -32,6 +32,15 @@ STEP_CASES = [
                                  precision="fp32", pf_max=0.4), 9, 20),
     ("rotated_sphere_fp32_d200", dict(dim=200, pop=48, kind="sphere", rotated=True,
                                       precision="fp32"), 2, 10),
+    # full benchmark size and launch configuration (ps 4096, D 100, FP32, rotated)
+    ("c2_full_size_first", dict(dim=100, pop=4096, kind="rastrigin", rotated=True,
+                                precision="fp32"), 1, 1000),
+    ("c2_full_size_late", dict(dim=100, pop=4096, kind="rastrigin", rotated=True,
+                               precision="fp32"), 640, 1000),
+    # many rank-sort splits with a ragged last block
+    ("large_pop_ragged_fp64", dict(dim=10, pop=5000, kind="rastrigin"), 3, 10),
+    ("large_pop_fp32_d3", dict(dim=3, pop=8192, kind="sphere", precision="fp32",
+                               pf_max=0.3), 2, 10),
 ]
 
 
@@ -59,6 +68,20 @@ def test_threshold_step_parity(kind, k):
     with g:
         X, F = random_state(p, 9, "fp32")
         compare_step(g, p, 4, X, F, "fp32")
+
+
+def test_kapur_full_size_config():
+    """Thresholding configuration: ps 1024, k = 16, 500 iterations."""
+    apo = need_gpu()
+    print("[parity] kapur ps1024 k16", flush=True)
+    img = gen.blob_image(1024, 1024, seed=1)
+    hist = gen.histogram_of(img)
+    g, p = make_pair(apo, dim=16, pop=1024, kind="kapur", precision="fp32", lb=0.0, ub=255.0,
+                     hist=hist, max_iter=500, seed=3)
+    with g:
+        for t in (1, 250, 500):
+            X, F = random_state(p, t, "fp32")
+            compare_step(g, p, t, X, F, "fp32")
 
 
 @pytest.mark.parametrize("precision,rotated,dim", [("fp64", False, 10), ("fp64", True, 24),
