@@ -25,7 +25,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Offsets of every device array inside the workspace (bytes, 256-aligned).
 struct Layout {
-    size_t X[2], F[2], perm, Fs, ctrl, p_ah, fscale, cnear, p_dr, lb, ub, shift, rotp, htab, hist,
+    size_t X[2], F, perm, Fs, ctrl, p_ah, fscale, cnear, p_dr, lb, ub, shift, rotp, htab, hist,
         best, trY, trF, trOp, total;
     int Dp, Nt, Ks;
 };
@@ -38,7 +38,10 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     const size_t es = o.precision == APO_FP64 ? 8 : 4;
     L.Dp = (int)align_up((size_t)dim, 64 / es);
     L.Nt = (dim + 15) / 16;
+    // k-steps of 4, padded with zeros to 32 (dim <= 128) or a multiple of 8,
+    // so the matrix-core loop runs unguarded in blocks of 8
     L.Ks = (dim + 3) / 4;
+    L.Ks = L.Ks <= 32 ? 32 : (L.Ks + 7) / 8 * 8;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -46,7 +49,7 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
         return at;
     };
     for (int b = 0; b < 2; ++b) L.X[b] = take((size_t)pop * L.Dp * es);
-    for (int b = 0; b < 2; ++b) L.F[b] = take((size_t)pop * es);
+    L.F = take((size_t)pop * es);
     L.perm = take((size_t)pop * 4);
     L.Fs = take((size_t)pop * es);
     L.ctrl = take(sizeof(Ctrl));
@@ -144,8 +147,8 @@ struct apo {
     bool own_ws;
     int32_t t;            // host mirror of completed iterations
     bool poisoned;
-    hipGraph_t graph;
-    hipGraphExec_t graph_exec;
+    hipGraph_t graph[2];          // [0]: one iteration, [1]: kGraphBlock iterations
+    hipGraphExec_t graph_exec[2];
     bool graph_tried;
     hipEvent_t ev[3];
     bool have_events;
@@ -181,8 +184,10 @@ const char *apo_strerror(int status) {
 
 static int destroy_impl(apo_t *h) {
     if (!h) return APO_OK;
-    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (int i = 0; i < 2; ++i) {
+        if (h->graph_exec[i]) (void)hipGraphExecDestroy(h->graph_exec[i]);
+        if (h->graph[i]) (void)hipGraphDestroy(h->graph[i]);
+    }
     if (h->have_events)
         for (int i = 0; i < 3; ++i) (void)hipEventDestroy(h->ev[i]);
     if (h->stream && !h->poisoned) (void)hipStreamSynchronize(h->stream);
@@ -252,8 +257,8 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     unsigned char *ws = h->ws;
     for (int b = 0; b < 2; ++b) {
         p.X[b] = ws + L.X[b];
-        p.F[b] = ws + L.F[b];
     }
+    p.F = ws + L.F;
     p.perm = (int32_t *)(ws + L.perm);
     p.Fs = ws + L.Fs;
     p.ctrl = (Ctrl *)(ws + L.ctrl);
@@ -298,14 +303,15 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     }
     if (p.rotated) {
         // B fragments of M^T for v_mfma 16x16x4: block (ks, nt), lane l holds
-        // B[k][n] = M[n][k] with k = 4 ks + l / 16, n = 16 nt + l % 16.
+        // B[k][n] = M[n][k] with k = Ks (l / 16) + ks, n = 16 nt + l % 16
+        // (the kernel reads A in the same k order).
         const size_t cnt = (size_t)L.Ks * L.Nt * 64;
         vrot.assign(cnt * h->es, 0);
         const double *M = opt->objective.rot;
         for (int ks = 0; ks < L.Ks; ++ks)
             for (int nt = 0; nt < L.Nt; ++nt)
                 for (int l = 0; l < 64; ++l) {
-                    const int k = 4 * ks + l / 16, n = 16 * nt + l % 16;
+                    const int k = L.Ks * (l / 16) + ks, n = 16 * nt + l % 16;
                     const double v = (k < dim && n < dim) ? M[(size_t)n * dim + k] : 0.0;
                     const size_t at = ((size_t)ks * L.Nt + nt) * 64 + l;
                     if (h->fp64)
@@ -362,6 +368,42 @@ int apo_step(apo_t *h) {
     return APO_OK;
 }
 
+// Iterations per replay of the block graph: long runs are submitted in
+// blocks so the host cost of a graph launch is paid once per block.
+static const int32_t kGraphBlock = 16;
+
+// Captures `iters` iterations (rank sort + step, in order) as one graph.
+// One iteration is iteration-invariant (the kernels read t from the device
+// control block), so the same graph serves every iteration of a run.
+static void capture_iterations(apo_t *h, int32_t iters, hipGraph_t *graph,
+                               hipGraphExec_t *exec) {
+    *graph = nullptr;
+    *exec = nullptr;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipError_t e = hipSuccess;
+    for (int32_t i = 0; i < iters && e == hipSuccess; ++i) {
+        e = apok::launch_rank(h->p, h->fp64, h->stream);
+        if (e == hipSuccess) e = apok::launch_step(h->p, h->fp64, h->stream);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e3 = hipStreamEndCapture(h->stream, &g);
+    if (e == hipSuccess && e3 == hipSuccess && g) {
+        hipGraphExec_t ge = nullptr;
+        if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess) {
+            *graph = g;
+            *exec = ge;
+        } else {
+            (void)hipGraphDestroy(g);
+        }
+    } else if (g) {
+        (void)hipGraphDestroy(g);
+    }
+    (void)hipGetLastError();
+}
+
 int apo_run(apo_t *h, int32_t iters) {
     if (!h || iters < 0) return APO_E_INVAL;
     if (h->poisoned) return APO_E_DEVICE;
@@ -370,35 +412,26 @@ int apo_run(apo_t *h, int32_t iters) {
     if (n <= 0) return 0;
     if (!h->graph_tried) {
         h->graph_tried = true;
-        // One iteration is iteration-invariant (the kernels read t from the
-        // device control block), so it is captured once and replayed.
-        if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            const hipError_t e1 = apok::launch_rank(h->p, h->fp64, h->stream);
-            const hipError_t e2 = apok::launch_step(h->p, h->fp64, h->stream);
-            hipGraph_t g = nullptr;
-            const hipError_t e3 = hipStreamEndCapture(h->stream, &g);
-            if (e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess && g) {
-                hipGraphExec_t ge = nullptr;
-                if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess) {
-                    h->graph = g;
-                    h->graph_exec = ge;
-                } else {
-                    (void)hipGraphDestroy(g);
-                }
-            } else if (g) {
-                (void)hipGraphDestroy(g);
-            }
-            (void)hipGetLastError();
-        }
+        capture_iterations(h, 1, &h->graph[0], &h->graph_exec[0]);
+        if (h->graph_exec[0] && h->T >= kGraphBlock)
+            capture_iterations(h, kGraphBlock, &h->graph[1], &h->graph_exec[1]);
     }
-    for (int32_t i = 0; i < n; ++i) {
-        if (h->graph_exec) {
-            APO_HIP(h, hipGraphLaunch(h->graph_exec, h->stream));
+    int32_t done = 0;
+    while (done < n) {
+        if (h->graph_exec[1] && n - done >= kGraphBlock) {
+            APO_HIP(h, hipGraphLaunch(h->graph_exec[1], h->stream));
+            done += kGraphBlock;
+            h->t += kGraphBlock;
+        } else if (h->graph_exec[0]) {
+            APO_HIP(h, hipGraphLaunch(h->graph_exec[0], h->stream));
+            ++done;
+            ++h->t;
         } else {
             const int rc = launch_iteration(h);
             if (rc != APO_OK) return rc;
+            ++done;
+            ++h->t;
         }
-        ++h->t;
     }
     return n;
 }
@@ -474,7 +507,7 @@ int apo_get_state(apo_t *h, double *X, double *F, int32_t *iter) {
         if (rc != APO_OK) return rc;
     }
     if (F) {
-        const int rc = copy_rows_out(h, h->p.F[cur], F, h->pop, 1, 1);
+        const int rc = copy_rows_out(h, h->p.F, F, h->pop, 1, 1);
         if (rc != APO_OK) return rc;
     }
     if (iter) *iter = h->t;
@@ -500,7 +533,7 @@ int apo_set_state(apo_t *h, const double *X, const double *F, int32_t iter) {
     c.t_next = iter;
     APO_HIP(h, hipStreamSynchronize(h->stream));
     APO_HIP(h, hipMemcpyAsync(h->p.X[cur], xb.data(), xb.size(), hipMemcpyHostToDevice, h->stream));
-    APO_HIP(h, hipMemcpyAsync(h->p.F[cur], fb.data(), fb.size(), hipMemcpyHostToDevice, h->stream));
+    APO_HIP(h, hipMemcpyAsync(h->p.F, fb.data(), fb.size(), hipMemcpyHostToDevice, h->stream));
     APO_HIP(h, hipMemcpyAsync(h->p.ctrl, &c, sizeof(c), hipMemcpyHostToDevice, h->stream));
     APO_HIP(h, hipStreamSynchronize(h->stream));
     h->t = iter;

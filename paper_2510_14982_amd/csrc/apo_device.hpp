@@ -87,8 +87,9 @@ struct Subset {
 
 // Domain-dependent parameters (everything except the keys).
 __device__ __forceinline__ void subset_shape(Subset &s, uint32_t n) {
-    uint32_t bits = 2;
-    while (bits < 32 && (1ull << bits) < (uint64_t)n) ++bits;
+    // b = max(2, ceil(log2 n))
+    uint32_t bits = n <= 1 ? 0u : 32u - (uint32_t)__builtin_clz(n - 1u);
+    bits = bits < 2 ? 2 : bits;
     s.n = n;
     s.rounds = bits <= 4 ? 24u : bits <= 6 ? 20u : bits <= 7 ? 16u : bits <= 9 ? 12u : 8u;
     s.table = bits <= 6;
@@ -229,6 +230,27 @@ __device__ __forceinline__ bool subset_has(const Subset &s, uint32_t x, uint32_t
     if (m >= s.n) return true;
     if (m == 0) return false;
     return subset_pi(s, x) < m;
+}
+
+// cos(pi x) in binary32: x = n + f with n the nearest integer and |f| <= 1/2,
+// cos(pi x) = (-1)^n cos(pi f), and cos(pi f) from its Taylor series in f^2
+// through the f^12 term (the first dropped term is below 7e-9 for
+// |f| <= 1/2), evaluated by Horner's rule with fused multiply-adds.
+__device__ __forceinline__ float cospi_f32(float x) {
+    const float n = rintf(x);
+    const float f = x - n;                               // exact
+    const float f2 = f * f;
+    float q = 1.92957431e-03f;                           //  pi^12 / 12!
+    q = __builtin_fmaf(q, f2, -2.58068914e-02f);         // -pi^10 / 10!
+    q = __builtin_fmaf(q, f2, 2.35330630e-01f);          //  pi^8 / 8!
+    q = __builtin_fmaf(q, f2, -1.33526277e+00f);         // -pi^6 / 6!
+    q = __builtin_fmaf(q, f2, 4.05871213e+00f);          //  pi^4 / 4!
+    q = __builtin_fmaf(q, f2, -4.93480220e+00f);         // -pi^2 / 2!
+    q = __builtin_fmaf(q, f2, 1.0f);
+    // n odd iff n/2 is not an integer (every binary32 integer of magnitude
+    // 2^24 or more is even, and n/2 is exact below that)
+    const float h = 0.5f * n;
+    return (h != rintf(h)) ? -q : q;
 }
 
 // ---------------------------------------------------------------------------

@@ -35,11 +35,12 @@ struct Params {
     int32_t kind;         // objective
     int32_t rotated;      // 1: z = M (x - o) through the packed matrix
     int32_t Nt, Ks;       // MFMA tiles: output column tiles of 16, k-steps of 4
+                          // (Ks padded to 32 or a multiple of 8; A and B zero there)
     int32_t trace;        // 1: write candidates to the trace buffers
     uint32_t seed_lo, seed_hi, run;
     double pf_max;
     void *X[2];           // [pop][Dp] positions, indexed by t & 1
-    void *F[2];           // [pop] fitness, indexed by t & 1
+    void *F;              // [pop] fitness by id (old values are read through Fs)
     int32_t *perm;        // [pop] rank -> id
     void *Fs;             // [pop] fitness in rank order (written with perm)
     Ctrl *ctrl;

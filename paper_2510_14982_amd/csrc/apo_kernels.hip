@@ -14,15 +14,17 @@ namespace apok {
 
 // ---------------------------------------------------------------------------
 // Rank sort.  rank(i) = #{j : (F_j, j) before (F_i, i)} in the fitness order,
-// so perm[rank(i)] = i.  One workgroup of 256 threads ranks 16 protozoa:
-// thread t owns protozoan i = 16 b + (t % 16) and the t / 16-th sixteenth of
-// every tile of order keys staged in LDS (read by broadcast); the sixteen
-// partial counts of each protozoan are added by shuffles and through LDS.
-// No workgroup depends on another.  Block 0 also opens the iteration: pf
-// (Eq. (11)), |Dr| and the Dr subset key schedule.
+// so perm[rank(i)] = i.  One workgroup of 256 threads ranks 8 protozoa.
+// Each thread holds the order keys of its share of the population in
+// registers (j = tid, tid + 256, ...), compares them against the 8 keys
+// being ranked (read by LDS broadcast) and keeps 8 counters, which are
+// summed over the workgroup by butterflies and LDS at the end.  No
+// workgroup depends on another.  Block 0 also opens the iteration: pf
+// (Eq. (11)), |Dr| and the Dr subset key schedule.  The sort also writes
+// the fitness in rank order (Fs), which the step reads instead of F.
 // ---------------------------------------------------------------------------
-constexpr int kRankTile = 4096;   // keys staged in LDS at a time (32 KB)
-constexpr int kRankPer = 16;      // protozoa ranked per workgroup
+constexpr int kRankPer = 8;       // protozoa ranked per workgroup
+constexpr int kRankJ = 16;        // keys per thread per pass (256 x 16 = 4096 per pass)
 
 template <typename T>
 struct RankKey;
@@ -41,25 +43,25 @@ struct RankKey<double> {  // 64-bit order key; equal keys fall back to the ids
     }
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void rank_kernel(Params p) {
-    __shared__ uint64_t keys[kRankTile];
-    __shared__ int32_t part[4][kRankPer];
-    const int tcur = p.ctrl->t;
-    const T *F = (const T *)p.F[tcur & 1];
-    const int ps = p.pop;
-    const int il = threadIdx.x & (kRankPer - 1), jg = threadIdx.x >> 4;   // jg in 0..15
-
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const Stream rng = stream_of(p);
-        const int t = tcur + 1;
-        const Words w0 = rng.block(TAG_ITER, 0, 0, (uint32_t)t);
-        const double pf = p.pf_max * uniform<double>(w0.w[0]);            // Eq. (11)
+// Opens iteration t = ctrl.t + 1 (one wavefront): pf of Eq. (11), |Dr|, the
+// Dr subset key schedule and the iteration's schedule scalars.  Lanes 0-2
+// draw the three Philox blocks; lane 0 finishes.
+__device__ __forceinline__ void open_iteration(const Params &p) {
+    const int lane = threadIdx.x & 63;
+    const int t = p.ctrl->t + 1;
+    const Stream rng = stream_of(p);
+    const Words w = rng.block(TAG_ITER, (uint32_t)(lane < 3 ? lane : 0), 0, (uint32_t)t);
+    const uint32_t u_pf = __shfl(w.w[0], 0, 64);
+    uint32_t k8[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        k8[e] = __shfl(w.w[e], 1, 64);
+        k8[4 + e] = __shfl(w.w[e], 2, 64);
+    }
+    if (lane == 0) {
+        const int ps = p.pop;
+        const double pf = p.pf_max * uniform<double>(u_pf);             // Eq. (11)
         p.ctrl->m_dr = (int32_t)ceil((double)ps * pf);                    // |Dr|
-        const Words b1 = rng.block(TAG_ITER, 1, 0, (uint32_t)t);
-        const Words b2 = rng.block(TAG_ITER, 2, 0, (uint32_t)t);
-        const uint32_t k8[8] = {b1.w[0], b1.w[1], b1.w[2], b1.w[3],
-                                b2.w[0], b2.w[1], b2.w[2], b2.w[3]};
         Subset drs;
         subset_init(drs, k8, (uint32_t)ps);
 #pragma unroll
@@ -69,36 +71,69 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
         p.ctrl->cnear = p.cnear[t];
         p.ctrl->t_next = t;
     }
+}
 
-    const int i = blockIdx.x * kRankPer + il;
-    const uint64_t ki = i < ps ? RankKey<T>::make(F[i], i) : ~0ull;
-    int32_t c = 0;
-    for (int base = 0; base < ps; base += kRankTile) {
-        const int n = min(kRankTile, ps - base);
-        __syncthreads();
-        for (int q = threadIdx.x; q < n; q += 256) keys[q] = RankKey<T>::make(F[base + q], base + q);
-        __syncthreads();
-        const int per = (n + 15) / 16;
-        const int q0 = jg * per, q1 = min(n, q0 + per);
-        int q = q0;
-        for (; q + 8 <= q1; q += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                c += RankKey<T>::before(keys[q + u], base + q + u, ki, i) ? 1 : 0;
-        }
-        for (; q < q1; ++q) c += RankKey<T>::before(keys[q], base + q, ki, i) ? 1 : 0;
+template <typename T>
+__global__ __launch_bounds__(256) void rank_kernel(Params p) {
+    __shared__ uint64_t s_ki[kRankPer];
+    __shared__ int32_t part[4][kRankPer];
+    const T *F = (const T *)p.F;
+    const int ps = p.pop;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i0 = blockIdx.x * kRankPer;
+
+    if (blockIdx.x == 0 && tid < 64) open_iteration(p);
+
+    if (tid < kRankPer) {
+        const T fi = F[i0 + tid < ps ? i0 + tid : ps - 1];
+        const uint64_t k = RankKey<T>::make(fi, i0 + tid);
+        s_ki[tid] = i0 + tid < ps ? k : ~0ull;
     }
-    // sum the 16 partial counts of protozoan il: lanes il + 16 {0..3} of each
-    // wavefront, then the four wavefronts
-    c += __shfl_xor(c, 16, 64);
-    c += __shfl_xor(c, 32, 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane < kRankPer) part[wave][lane] = c;
+    int32_t cnt[kRankPer];
+#pragma unroll
+    for (int q = 0; q < kRankPer; ++q) cnt[q] = 0;
     __syncthreads();
-    if (threadIdx.x < kRankPer && i < ps) {
-        const int rank = part[0][il] + part[1][il] + part[2][il] + part[3][il];
-        p.perm[rank] = i;
-        ((T *)p.Fs)[rank] = F[i];
+    uint64_t ki[kRankPer];
+#pragma unroll
+    for (int q = 0; q < kRankPer; ++q) ki[q] = s_ki[q];
+
+    for (int base = 0; base < ps; base += 256 * kRankJ) {
+        // all loads issued before any key is formed (an index past the end
+        // reads the last element and is then replaced by the padding key)
+        T fj[kRankJ];
+#pragma unroll
+        for (int u = 0; u < kRankJ; ++u) {
+            const int j = base + 256 * u + tid;
+            fj[u] = F[j < ps ? j : ps - 1];
+        }
+        uint64_t kj[kRankJ];
+#pragma unroll
+        for (int u = 0; u < kRankJ; ++u) {
+            const int j = base + 256 * u + tid;
+            const uint64_t k = RankKey<T>::make(fj[u], j);
+            kj[u] = j < ps ? k : ~0ull;   // ~0 sorts after all
+        }
+#pragma unroll
+        for (int u = 0; u < kRankJ; ++u) {
+            const int j = base + 256 * u + tid;
+#pragma unroll
+            for (int q = 0; q < kRankPer; ++q)
+                cnt[q] += RankKey<T>::before(kj[u], j, ki[q], i0 + q) ? 1 : 0;
+        }
+    }
+    // a padding key equals ~0 and never precedes a real key except another
+    // padding key; real keys with id < ps are all below ~0, and the double
+    // version's id tie-break only applies among equal real keys
+#pragma unroll
+    for (int q = 0; q < kRankPer; ++q) {
+        const int32_t v = group_sum<64>(cnt[q]);
+        if (lane == 0) part[wave][q] = v;
+    }
+    __syncthreads();
+    if (tid < kRankPer && i0 + tid < ps) {
+        const int rank = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+        p.perm[rank] = i0 + tid;
+        ((T *)p.Fs)[rank] = F[i0 + tid];
     }
 }
 
@@ -110,7 +145,7 @@ template <typename T>
 __global__ __launch_bounds__(1024) void best_kernel(Params p, int cur, double *out_row) {
     __shared__ uint64_t sk[1024];
     __shared__ int32_t si[1024];
-    const T *F = (const T *)p.F[cur];
+    const T *F = (const T *)p.F;
     uint64_t bk = ~0ull;
     int32_t bi = 0x7FFFFFFF;
     for (int i = threadIdx.x; i < p.pop; i += 1024) {
@@ -168,21 +203,27 @@ __global__ void zero_u32_kernel(uint32_t *a, int n) {
     if (i < n) a[i] = 0u;
 }
 
-// 8-bit histogram: per-wavefront LDS copies absorb runs of equal grey
-// levels; each workgroup merges its copies into the output once.  The bytes
-// before the first 16-byte boundary and after the last one are counted one
-// by one; the rest is read as 16-byte vectors.
+// 8-bit histogram.  Sixteen LDS copies per workgroup, chosen by lane % 16,
+// so lanes that meet the same grey level (frequent in images made of
+// uniform regions) mostly hit different copies; copies are 257 words apart
+// so equal levels of different copies sit in different banks.  Each
+// workgroup adds its copies into the output once.  Bytes before the first
+// and after the last 16-byte boundary are counted one by one; the rest is
+// read as 16-byte vectors.
+constexpr int kHistCopies = 16;
+constexpr int kHistStride = 257;
+
 __global__ __launch_bounds__(256) void hist_kernel(const uint8_t *img, uint64_t n, uint32_t *hist) {
-    __shared__ uint32_t h[4][256];
-    const int wave = threadIdx.x >> 6;
-    for (int b = threadIdx.x; b < 4 * 256; b += 256) (&h[0][0])[b] = 0u;
+    __shared__ uint32_t h[kHistCopies * kHistStride];
+    uint32_t *mine = h + (threadIdx.x & (kHistCopies - 1)) * kHistStride;
+    for (int b = threadIdx.x; b < kHistCopies * kHistStride; b += 256) h[b] = 0u;
     __syncthreads();
     uint64_t head = (16u - ((uintptr_t)img & 15u)) & 15u;
     if (head > n) head = n;
     const uint64_t nvec = (n - head) / 16;
     const uint64_t tid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
-    if (tid < head) atomicAdd(&h[wave][img[tid]], 1u);
+    if (tid < head) atomicAdd(&mine[img[tid]], 1u);
     const uint4 *v = (const uint4 *)(img + head);
     for (uint64_t i = tid; i < nvec; i += stride) {
         const uint4 q = v[i];
@@ -190,13 +231,15 @@ __global__ __launch_bounds__(256) void hist_kernel(const uint8_t *img, uint64_t 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&h[wave][(w[j] >> (8 * b)) & 0xFFu], 1u);
+            for (int b = 0; b < 4; ++b) atomicAdd(&mine[(w[j] >> (8 * b)) & 0xFFu], 1u);
         }
     }
-    for (uint64_t i = head + nvec * 16 + tid; i < n; i += stride) atomicAdd(&h[wave][img[i]], 1u);
+    for (uint64_t i = head + nvec * 16 + tid; i < n; i += stride) atomicAdd(&mine[img[i]], 1u);
     __syncthreads();
     for (int b = threadIdx.x; b < 256; b += 256) {
-        const uint32_t s = h[0][b] + h[1][b] + h[2][b] + h[3][b];
+        uint32_t s = 0;
+#pragma unroll
+        for (int c = 0; c < kHistCopies; ++c) s += h[c * kHistStride + b];
         if (s) atomicAdd(&hist[b], s);
     }
 }

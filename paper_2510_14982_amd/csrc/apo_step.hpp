@@ -41,9 +41,9 @@ __device__ __forceinline__ void store4(T *p, const T v[4]) {
 }
 
 // cos(2 pi z): binary64 follows the textbook expression; binary32 uses
-// cospi(2z), whose argument is exact.
+// cospi_f32(2z): 2z is exact and the reduction to [-1/2, 1/2] is exact.
 __device__ __forceinline__ double cos2pi(double z) { return cos(2.0 * kPi * z); }
-__device__ __forceinline__ float cos2pi(float z) { return cospif(2.0f * z); }
+__device__ __forceinline__ float cos2pi(float z) { return apok::cospi_f32(2.0f * z); }
 
 __device__ __forceinline__ Stream stream_of(const Params &p) {
     Stream s;
@@ -79,36 +79,72 @@ __device__ __forceinline__ T weight(T fa, T fb) {
     return exp(-fabs(fa / (fb + T(kEps))));
 }
 
+// The protozoan's draws and every load that depends only on them, issued
+// before the decisions so they overlap the decision arithmetic: its id and
+// old fitness, and the ids / fitness of the first neighbour pair under both
+// foraging modes (k-, k+ and j of Eq. (6); i-1, i+1 of Eq. (8)).
+template <typename T>
+struct Draws {
+    Words s0, k1, k2, q3;
+    double p_dr;
+    int32_t idj, ida[2], idb[2];   // [0] autotroph pair, [1] heterotroph pair
+    T fa[2], fb[2];
+};
+
 // `lane0` is the wavefront lane of the group's first lane; the group has at
 // least four lanes, and its lanes 0..3 each draw one of the rank's blocks
 // 0..3, which are then exchanged across the group.
-template <typename T, int NPMAX, int G>
-__device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T *F,
-                                          int lane0, int lane, uint32_t *mwords,
-                                          Plan<T, NPMAX> &c) {
+template <typename T, int NPMAX>
+__device__ __forceinline__ void plan_draws(const Params &p, int r, int t, int lane0, int lane,
+                                           Plan<T, NPMAX> &c, Draws<T> &d) {
     const Stream rng = stream_of(p);
-    const int ps = p.pop, D = p.dim;
+    const int ps = p.pop;
     const T *Fs = (const T *)p.Fs;   // fitness by rank, written by the sort
     c.r = r;
     c.id = p.perm[r];
     c.fold = Fs[r];
-    c.fac = T(0); c.srep = T(0); c.sgn = T(1); c.cn = T(p.ctrl->cnear); c.idj = 0;
+    d.p_dr = p.p_dr[r];
     const Words mine = rng.block(TAG_RANK, (uint32_t)(lane & 3), (uint32_t)r, (uint32_t)t);
-    Words s0, k1, k2, q3;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        s0.w[e] = __shfl(mine.w[e], lane0 + 0, 64);
-        k1.w[e] = __shfl(mine.w[e], lane0 + 1, 64);
-        k2.w[e] = __shfl(mine.w[e], lane0 + 2, 64);
-        q3.w[e] = __shfl(mine.w[e], lane0 + 3, 64);
+        d.s0.w[e] = __shfl(mine.w[e], lane0 + 0, 64);
+        d.k1.w[e] = __shfl(mine.w[e], lane0 + 1, 64);
+        d.k2.w[e] = __shfl(mine.w[e], lane0 + 2, 64);
+        d.q3.w[e] = __shfl(mine.w[e], lane0 + 3, 64);
     }
-    const uint32_t keys[8] = {k1.w[0], k1.w[1], k1.w[2], k1.w[3],
-                              k2.w[0], k2.w[1], k2.w[2], k2.w[3]};
+    // words 1, 2, 3 of the sequence at block 3: j, k-_1, k+_1
+    const int j = (int)bounded(d.q3.w[1], (uint32_t)ps);
+    const int km = r == 0 ? r : (int)bounded(d.q3.w[2], (uint32_t)r);
+    const int kp = r == ps - 1 ? r : r + 1 + (int)bounded(d.q3.w[3], (uint32_t)(ps - 1 - r));
+    const int a = r - 1 < 0 ? 0 : r - 1;
+    const int b = r + 1 > ps - 1 ? ps - 1 : r + 1;
+    d.idj = p.perm[j];
+    d.ida[0] = p.perm[km];
+    d.idb[0] = p.perm[kp];
+    d.ida[1] = p.perm[a];
+    d.idb[1] = p.perm[b];
+    d.fa[0] = Fs[km];
+    d.fb[0] = Fs[kp];
+    d.fa[1] = Fs[a];
+    d.fb[1] = Fs[b];
+}
+
+// The decisions of Algorithm 1 for rank r: Dr membership, the operation
+// (Eqs. (12), (13)), the mask size, the scalars and the neighbour pairs.
+template <typename T, int NPMAX>
+__device__ __forceinline__ void plan_decide(const Params &p, int r, int t, const Draws<T> &d,
+                                            Plan<T, NPMAX> &c) {
+    const Stream rng = stream_of(p);
+    const int ps = p.pop, D = p.dim;
+    const T *Fs = (const T *)p.Fs;
+    c.fac = T(0); c.srep = T(0); c.cn = T(p.ctrl->cnear); c.idj = 0;
+    const uint32_t keys[8] = {d.k1.w[0], d.k1.w[1], d.k1.w[2], d.k1.w[3],
+                              d.k2.w[0], d.k2.w[1], d.k2.w[2], d.k2.w[3]};
     subset_init(c.mask, keys, (uint32_t)D);
-    const double u_op = uniform<double>(s0.w[0]);
-    const double u_f = uniform<double>(s0.w[1]);
-    const double u_rep = uniform<double>(s0.w[2]);
-    const double sgn = uniform<double>(s0.w[3]) < 0.5 ? 1.0 : -1.0;
+    const double u_op = uniform<double>(d.s0.w[0]);
+    const double u_f = uniform<double>(d.s0.w[1]);
+    const double u_rep = uniform<double>(d.s0.w[2]);
+    const double sgn = uniform<double>(d.s0.w[3]) < 0.5 ? 1.0 : -1.0;
     c.sgn = T(sgn);
 
     bool in_dr;
@@ -119,83 +155,126 @@ __device__ __forceinline__ void make_plan(const Params &p, int r, int t, const T
         for (int i = 0; i < 24; ++i) drs.k[i] = p.ctrl->dr_keys[i];
         in_dr = subset_has(drs, (uint32_t)r, (uint32_t)p.ctrl->m_dr);
     }
+#pragma unroll
+    for (int k = 0; k < NPMAX; ++k) {
+        c.idm[k] = c.idp[k] = 0;
+        c.w[k] = T(0);
+    }
     if (in_dr) {
-        if (p.p_dr[r] > u_op) {                       // Eq. (13) -> dormancy
+        if (d.p_dr > u_op) {                          // Eq. (13) -> dormancy
             c.op = OP_DORMANCY;
             c.m = (uint32_t)D;
         } else {                                      // reproduction, |M_r| = ceil(D rand)
             c.op = OP_REPRODUCTION;
-            const uint64_t k = q3.w[0] >> 9;
+            const uint64_t k = d.q3.w[0] >> 9;
             c.m = (uint32_t)(((uint64_t)D * (2ull * k + 1ull) + (1ull << 24) - 1ull) >> 24);
             c.srep = T(sgn * u_rep);
         }
-    } else {
-        c.fac = T(u_f * p.ctrl->fscale);
-        c.m = (uint32_t)(((uint64_t)D * (uint64_t)(r + 1) + (uint64_t)ps - 1ull) / (uint64_t)ps);
-        if (p.ctrl->p_ah > u_op) {                    // Eq. (12) -> autotroph
-            c.op = OP_AUTOTROPH;
-            c.idj = p.perm[bounded(q3.w[1], (uint32_t)ps)];
+        return;
+    }
+    c.fac = T(u_f * p.ctrl->fscale);
+    c.m = (uint32_t)(((uint64_t)D * (uint64_t)(r + 1) + (uint64_t)ps - 1ull) / (uint64_t)ps);
+    const bool autotroph = p.ctrl->p_ah > u_op;       // Eq. (12)
+    c.op = autotroph ? OP_AUTOTROPH : OP_HETEROTROPH;
+    c.idj = d.idj;
+    c.idm[0] = autotroph ? d.ida[0] : d.ida[1];
+    c.idp[0] = autotroph ? d.idb[0] : d.idb[1];
+    c.w[0] = weight<T>(autotroph ? d.fa[0] : d.fa[1],
+                       autotroph ? d.fb[0] : d.fb[1]);  // Eq. (7) / Eq. (10)
 #pragma unroll
-            for (int k = 0; k < NPMAX; ++k) {
-                if (k < p.np) {
-                    // words 2k+2 (k-) and 2k+3 (k+) of the sequence starting at block 3
-                    uint32_t wm, wp;
-                    if (k == 0) {
-                        wm = q3.w[2];
-                        wp = q3.w[3];
-                    } else {
-                        const Words b = rng.block(TAG_RANK, 3 + (uint32_t)(2 * k + 2) / 4,
-                                                  (uint32_t)r, (uint32_t)t);
-                        wm = b.w[(2 * k + 2) & 3];
-                        wp = b.w[(2 * k + 3) & 3];
-                    }
-                    const int km = r == 0 ? r : (int)bounded(wm, (uint32_t)r);
-                    const int kp = r == ps - 1 ? r : r + 1 + (int)bounded(wp, (uint32_t)(ps - 1 - r));
-                    c.idm[k] = p.perm[km];
-                    c.idp[k] = p.perm[kp];
-                    c.w[k] = weight<T>(Fs[km], Fs[kp]);
-                } else {
-                    c.idm[k] = c.idp[k] = 0;
-                    c.w[k] = T(0);
-                }
+    for (int k = 1; k < NPMAX; ++k) {
+        if (k < p.np) {
+            int ra, rb;
+            if (autotroph) {
+                // words 2k+2 (k-) and 2k+3 (k+) of the sequence starting at block 3
+                const Words bw = rng.block(TAG_RANK, 3 + (uint32_t)(2 * k + 2) / 4, (uint32_t)r,
+                                           (uint32_t)t);
+                const uint32_t wm = bw.w[(2 * k + 2) & 3], wp = bw.w[(2 * k + 3) & 3];
+                ra = r == 0 ? r : (int)bounded(wm, (uint32_t)r);
+                rb = r == ps - 1 ? r : r + 1 + (int)bounded(wp, (uint32_t)(ps - 1 - r));
+            } else {                                  // i - k and i + k held in [1, ps]
+                ra = r - (k + 1) < 0 ? 0 : r - (k + 1);
+                rb = r + (k + 1) > ps - 1 ? ps - 1 : r + (k + 1);
             }
-        } else {                                      // heterotroph
-            c.op = OP_HETEROTROPH;
-#pragma unroll
-            for (int k = 0; k < NPMAX; ++k) {
-                if (k < p.np) {
-                    const int a = r - (k + 1) < 0 ? 0 : r - (k + 1);
-                    const int b = r + (k + 1) > ps - 1 ? ps - 1 : r + (k + 1);
-                    c.idm[k] = p.perm[a];
-                    c.idp[k] = p.perm[b];
-                    c.w[k] = weight<T>(Fs[a], Fs[b]);
-                } else {
-                    c.idm[k] = c.idp[k] = 0;
-                    c.w[k] = T(0);
-                }
-            }
+            c.idm[k] = p.perm[ra];
+            c.idp[k] = p.perm[rb];
+            c.w[k] = weight<T>(Fs[ra], Fs[rb]);
         }
     }
+}
+
+template <typename T, int NPMAX, int G>
+__device__ __forceinline__ void plan_mask(const Params &p, Plan<T, NPMAX> &c, uint32_t *mwords,
+                                          int lane) {
     c.mw = mwords;
     if (c.op != OP_DORMANCY)
-        subset_mask_group<G>(c.mask, c.m, mwords, (D + 31) / 32, lane);
+        subset_mask_group<G>(c.mask, c.m, mwords, (p.dim + 31) / 32, lane);
+}
+
+// Rows a lane reads for its NCH chunks of 4 coordinates, loaded before the
+// mask is built: its own row and the neighbours of the first pair (with X_j
+// for an autotroph).
+template <typename T, int NCH>
+struct Rows {
+    typedef typename V4<T>::type v4;
+    v4 x[NCH];            // own row
+    v4 xj[NCH];           // X_j of Eq. (6)
+    v4 am[NCH], ap[NCH];  // first pair of Eq. (6): k-, k+
+    v4 hm[NCH], hp[NCH];  // first pair of Eq. (8): i-1, i+1
+};
+
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type load4v(const T *p) {
+    return *reinterpret_cast<const typename V4<T>::type *>(p);
+}
+
+// Own row only (c.id known), or the neighbour rows.  With `both` the first
+// pairs of both foraging modes and X_j are requested before the operation
+// is decided (from the draws alone); otherwise only the decided ones.
+template <typename T, int NPMAX, int NCH, int G>
+__device__ __forceinline__ void load_rows(const Params &p, const Plan<T, NPMAX> &c,
+                                          const Draws<T> &d, int lane, const T *Xc, bool own,
+                                          bool neighbours, bool both, Rows<T, NCH> &rw) {
+    const int D = p.dim, Dp = p.Dp;
+    const typename V4<T>::type zero = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int d0 = 4 * (lane + ch * G);
+        const bool in = d0 < D;
+        if (own) rw.x[ch] = in ? load4v(Xc + (size_t)c.id * Dp + d0) : zero;
+        if (neighbours && both) {
+            rw.xj[ch] = in ? load4v(Xc + (size_t)d.idj * Dp + d0) : zero;
+            rw.am[ch] = in ? load4v(Xc + (size_t)d.ida[0] * Dp + d0) : zero;
+            rw.ap[ch] = in ? load4v(Xc + (size_t)d.idb[0] * Dp + d0) : zero;
+            rw.hm[ch] = in ? load4v(Xc + (size_t)d.ida[1] * Dp + d0) : zero;
+            rw.hp[ch] = in ? load4v(Xc + (size_t)d.idb[1] * Dp + d0) : zero;
+        } else if (neighbours) {   // the decided pair goes to am / ap
+            const bool fo = in && c.op >= OP_AUTOTROPH;
+            rw.xj[ch] = (fo && c.op == OP_AUTOTROPH) ? load4v(Xc + (size_t)c.idj * Dp + d0) : zero;
+            rw.am[ch] = fo ? load4v(Xc + (size_t)c.idm[0] * Dp + d0) : zero;
+            rw.ap[ch] = fo ? load4v(Xc + (size_t)c.idp[0] * Dp + d0) : zero;
+        }
+    }
 }
 
 // Candidate values of the four coordinates d0..d0+3 of one protozoan,
-// clamped to the bounds.  x receives the row's own values.  Coordinates at
-// or beyond D are set to zero (the row padding).
+// clamped to the bounds, from the preloaded rows x (own), xj, xm, xp (first
+// pair); further pairs are read here.  Coordinates at or beyond D are set
+// to zero (the row padding), in x as well.
 template <typename T, int NPMAX>
 __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX> &c, int t,
-                                           bool init, int d0, const T *Xc, T x[4], T y[4]) {
+                                           bool init, int d0, const T *Xc,
+                                           typename V4<T>::type &x,
+                                           const typename V4<T>::type &xj,
+                                           const typename V4<T>::type &am,
+                                           const typename V4<T>::type &ap,
+                                           const typename V4<T>::type &hm,
+                                           const typename V4<T>::type &hp, T y[4]) {
     const int D = p.dim, Dp = p.Dp;
     T lb[4], ub[4];
     load4((const T *)p.lb + d0, lb);
     load4((const T *)p.ub + d0, ub);
-    if (init) {
-        x[0] = x[1] = x[2] = x[3] = T(0);
-    } else {
-        load4(Xc + (size_t)c.id * Dp + d0, x);
-    }
+    if (init) x = typename V4<T>::type{T(0), T(0), T(0), T(0)};
     const Stream rng = stream_of(p);
     T U[4] = {T(0), T(0), T(0), T(0)};
     if (init) {
@@ -219,21 +298,25 @@ __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX>
                 y[e] = x[e] + c.srep * (lb[e] + U[e] * (ub[e] - lb[e]));        // Eq. (2)
         }
     } else {
-        T acc[4] = {T(0), T(0), T(0), T(0)};
+        T acc[4];
+        const bool au = c.op == OP_AUTOTROPH;
 #pragma unroll
-        for (int k = 0; k < NPMAX; ++k) {
+        for (int e = 0; e < 4; ++e) {
+            const T xm = au ? am[e] : hm[e], xp = au ? ap[e] : hp[e];
+            acc[e] = T(0) + c.w[0] * (xm - xp);
+        }
+#pragma unroll
+        for (int k = 1; k < NPMAX; ++k) {
             if (k < p.np) {
-                T xm[4], xp[4];
-                load4(Xc + (size_t)c.idm[k] * Dp + d0, xm);
-                load4(Xc + (size_t)c.idp[k] * Dp + d0, xp);
+                T xmk[4], xpk[4];
+                load4(Xc + (size_t)c.idm[k] * Dp + d0, xmk);
+                load4(Xc + (size_t)c.idp[k] * Dp + d0, xpk);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc[e] = acc[e] + c.w[k] * (xm[e] - xp[e]);
+                for (int e = 0; e < 4; ++e) acc[e] = acc[e] + c.w[k] * (xmk[e] - xpk[e]);
             }
         }
         const T npd = T(p.np);
         if (c.op == OP_AUTOTROPH) {
-            T xj[4];
-            load4(Xc + (size_t)c.idj * Dp + d0, xj);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 y[e] = x[e];
@@ -271,19 +354,25 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     const int t = init ? 0 : p.ctrl->t_next;
     const int src = (t + 1) & 1, dst = t & 1;
     const T *Xc = (const T *)p.X[src];
-    const T *Fc = (const T *)p.F[src];
+    const T *Fc = (const T *)p.Fs;   // old fitness, in rank order
     T *Xn = (T *)p.X[dst];
-    T *Fn = (T *)p.F[dst];
+    T *Fn = (T *)p.F;
 
     constexpr int MW = (4 * G * NCH + 31) / 32;
     __shared__ uint32_t mwords[256 / G][MW];
     Plan<T, NPMAX> c;
+    Rows<T, NCH> rw;
     if (init) {
         c.op = OP_DORMANCY; c.id = item; c.r = item; c.m = (uint32_t)D; c.fold = T(0);
     } else {
-        make_plan<T, NPMAX, G>(p, item, t, Fc, (threadIdx.x & 63) & ~(G - 1), lane,
-                               mwords[threadIdx.x / G], c);
+        Draws<T> d;
+        plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
+        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, false, false, rw);
+        plan_decide<T, NPMAX>(p, item, t, d, c);
+        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, false, true, false, rw);
+        plan_mask<T, NPMAX, G>(p, c, mwords[threadIdx.x / G], lane);
     }
+    (void)Fc;
 
     T xs[NCH][4], ys[NCH][4];
     const T *o = (const T *)p.shift;
@@ -293,7 +382,10 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     for (int ch = 0; ch < NCH; ++ch) {
         const int d0 = 4 * (lane + ch * G);
         if (d0 < D) {
-            candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, xs[ch], ys[ch]);
+            candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, rw.x[ch], rw.xj[ch], rw.am[ch],
+                                 rw.ap[ch], rw.am[ch], rw.ap[ch], ys[ch]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xs[ch][e] = rw.x[ch][e];
             T ov[4];
             load4(o + d0, ov);
 #pragma unroll
@@ -432,6 +524,19 @@ __device__ __forceinline__ double threshold_objective(const Params &p, const T *
     return -total;
 }
 
+// LDS row stride of the tile: room for the padded k range of the A operand,
+// odd so the 16 rows of an A fragment fall in different banks.
+// LDS row stride (elements) of the tile's row buffers.  The matrix-core A
+// operand is read as 16-byte vectors by 16 lanes of 16 different rows at a
+// time; a stride of 4 words (mod 64) puts those rows in 16 distinct groups
+// of four banks.  The stride is a multiple of 16 bytes, so rows are also
+// written as 16-byte vectors.
+__host__ __device__ inline int tile_row_stride(const Params &p, int es) {
+    const int w = p.Dp > 4 * p.Ks ? p.Dp : 4 * p.Ks;
+    const int mod = 256 / es, off = 16 / es;      // 64 words and 4 words, in elements
+    return (w - off + mod - 1) / mod * mod + off;
+}
+
 template <typename T, int G, int NCH, int NPMAX>
 __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     constexpr int NT = 512, TM = kTileRanks, GROUPS = NT / G;
@@ -440,16 +545,18 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     __shared__ uint32_t s_mwords[GROUPS][(4 * G * NCH + 31) / 32];
     __shared__ T s_fold[TM], s_fnew[TM];
     const int D = p.dim, Dp = p.Dp;
-    const int LS = Dp + 1, LZ = p.Nt * 16 + 1;
-    T *Ys = (T *)smem;
-    T *Xs = Ys + TM * LS;
-    T *Zs = Xs + TM * LS;
+    const int LS = tile_row_stride(p, (int)sizeof(T)), LZ = p.Nt * 16 + 1;
+    T *Ys = (T *)smem;        // clamped candidates
+    T *Xs = Ys + TM * LS;     // own rows
+    T *As = Xs + TM * LS;     // y - o, the matrix-core A operand
+    T *Zs = As + TM * LS;     // z = M (y - o) when a coordinate's neighbour is needed
+    __shared__ T s_p1[TM][32], s_p2[TM][32];   // per column-tile partial sums
     const int t = init ? 0 : p.ctrl->t_next;
     const int src = (t + 1) & 1, dst = t & 1;
     const T *Xc = (const T *)p.X[src];
-    const T *Fc = (const T *)p.F[src];
+    const T *Fc = (const T *)p.Fs;   // old fitness, in rank order
     T *Xn = (T *)p.X[dst];
-    T *Fn = (T *)p.F[dst];
+    T *Fn = (T *)p.F;
     const T *o = (const T *)p.shift;
     const int r0 = blockIdx.x * TM;
     const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
@@ -459,13 +566,22 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     constexpr int PRE = sizeof(T) == 4 ? 32 : 16;
     T bpre[PRE];
     {
-        const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
         const T *B = (const T *)p.rotp;
+        if (p.rotated && wave < p.Nt) {
+            // the packed K range holds at least 32 steps (zero padded)
 #pragma unroll
-        for (int ks = 0; ks < PRE; ++ks)
-            bpre[ks] = (p.rotated && wave < p.Nt && ks < p.Ks)
-                           ? B[((size_t)ks * p.Nt + wave) * 64 + l]
-                           : T(0);
+            for (int ks = 0; ks < PRE; ++ks) bpre[ks] = B[((size_t)ks * p.Nt + wave) * 64 + l];
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < PRE; ++ks) bpre[ks] = T(0);
+        }
+    }
+
+    // zero the padded k range of the A operand
+    for (int q = threadIdx.x; q < TM * (4 * p.Ks - D); q += NT) {
+        const int row = q / (4 * p.Ks - D), col = D + q % (4 * p.Ks - D);
+        As[row * LS + col] = T(0);
     }
 
     // phase 1: candidates into LDS
@@ -473,23 +589,42 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
         const int item = r0 + row;
         if (item < p.pop) {
             Plan<T, NPMAX> c;
+            Rows<T, NCH> rw;
             if (init) {
                 c.op = OP_DORMANCY; c.id = item; c.r = item; c.m = (uint32_t)D; c.fold = T(0);
             } else {
-                make_plan<T, NPMAX, G>(p, item, t, Fc, (threadIdx.x & 63) & ~(G - 1), lane,
-                                       s_mwords[grp], c);
+                Draws<T> d;
+                plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
+                load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, true, rw);
+                plan_decide<T, NPMAX>(p, item, t, d, c);
+                plan_mask<T, NPMAX, G>(p, c, s_mwords[grp], lane);
             }
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int d0 = 4 * (lane + ch * G);
                 if (d0 < D) {
-                    T x[4], y[4];
-                    candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, x, y);
+                    T y[4];
+                    candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, rw.x[ch], rw.xj[ch],
+                                         rw.am[ch], rw.ap[ch], rw.hm[ch], rw.hp[ch], y);
+                    T ov[4], a[4], xo[4];
+                    load4(o + d0, ov);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        if (d0 + e < D) {
-                            Ys[row * LS + d0 + e] = y[e];
-                            Xs[row * LS + d0 + e] = x[e];
+                        a[e] = y[e] - ov[e];
+                        xo[e] = rw.x[ch][e];
+                    }
+                    if (d0 + 4 <= D) {
+                        store4(Ys + row * LS + d0, y);
+                        store4(Xs + row * LS + d0, xo);
+                        store4(As + row * LS + d0, a);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            if (d0 + e < D) {
+                                Ys[row * LS + d0 + e] = y[e];
+                                Xs[row * LS + d0 + e] = xo[e];
+                                As[row * LS + d0 + e] = a[e];
+                            }
                         }
                     }
                 }
@@ -500,7 +635,7 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
                 s_fold[row] = c.fold;
             }
         } else {
-            for (int d = lane; d < D; d += G) Ys[row * LS + d] = Xs[row * LS + d] = T(0);
+            for (int d = lane; d < D; d += G) Ys[row * LS + d] = Xs[row * LS + d] = As[row * LS + d] = T(0);
             if (lane == 0) s_id[row] = -1;
         }
     }
@@ -515,29 +650,59 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
         const typename V4<T>::type zero = {T(0), T(0), T(0), T(0)};
         const T *B = (const T *)p.rotp;
         const int i = l & 15;
+        // the contraction index of step ks in lane l is k = Ks (l / 16) + ks
+        // (the host packs B with the same order), so a lane's A values are
+        // contiguous: A[i][Ks (l / 16) + ks] at Arow[ks]
+        const T *Arow = As + i * LS + (l >> 4) * p.Ks;
         for (int nt = wave; nt < p.Nt; nt += NT / 64) {
             typename V4<T>::type acc = zero;
-            int ks0 = 0;
-            if (nt == wave) {   // fragments already in registers
+            if (nt == wave && p.Ks == PRE) {
+                // fragments already in registers: one straight run
+                T a[PRE];
 #pragma unroll
-                for (int ks = 0; ks < PRE; ++ks) {
-                    if (ks < p.Ks) {
-                        const int k = 4 * ks + (l >> 4);
-                        const T a = k < D ? Ys[i * LS + k] - o[k] : T(0);
-                        acc = mfma16x16x4(a, bpre[ks], acc);
+                for (int q = 0; q < PRE / 4; ++q) load4(Arow + 4 * q, a + 4 * q);
+#pragma unroll
+                for (int ks = 0; ks < PRE; ++ks) acc = mfma16x16x4(a[ks], bpre[ks], acc);
+            } else {
+                for (int k0 = 0; k0 < p.Ks; k0 += 8) {
+                    T a[8], b[8];
+                    load4(Arow + k0, a);
+                    load4(Arow + k0 + 4, a + 4);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) b[u] = B[((size_t)(k0 + u) * p.Nt + nt) * 64 + l];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc = mfma16x16x4(a[u], b[u], acc);
+                }
+            }
+            if (p.kind == K_ROSENBROCK) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Zs[mfma_out_row<T>(l, v) * LZ + 16 * nt + (l & 15)] = acc[v];
+            } else {
+                // separable objectives straight from the accumulators: the
+                // 16 columns of this tile summed per row (butterfly over the
+                // 16 lanes of a row group), one partial per (row, tile)
+                const bool valid = 16 * nt + (l & 15) < D;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const T z = acc[v];
+                    T g1 = T(0), g2 = T(0);
+                    if (valid) {
+                        if (p.kind == K_RASTRIGIN) {
+                            g1 = z * z - T(10) * cos2pi(z) + T(10);
+                        } else {
+                            g1 = z * z;
+                            if (p.kind == K_ACKLEY) g2 = cos2pi(z);
+                        }
+                    }
+                    g1 = group_sum<16>(g1);
+                    g2 = group_sum<16>(g2);
+                    if ((l & 15) == 0) {
+                        s_p1[mfma_out_row<T>(l, v)][nt] = g1;
+                        s_p2[mfma_out_row<T>(l, v)][nt] = g2;
                     }
                 }
-                ks0 = PRE;
             }
-#pragma unroll 8
-            for (int ks = ks0; ks < p.Ks; ++ks) {
-                const int k = 4 * ks + (l >> 4);
-                const T a = k < D ? Ys[i * LS + k] - o[k] : T(0);
-                const T b = B[((size_t)ks * p.Nt + nt) * 64 + l];
-                acc = mfma16x16x4(a, b, acc);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Zs[mfma_out_row<T>(l, v) * LZ + 16 * nt + (l & 15)] = acc[v];
         }
         __syncthreads();
     }
@@ -548,15 +713,27 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
             int *ts = (int *)Zs + threadIdx.x * (D + 1);
             s_fnew[threadIdx.x] = T(threshold_objective<T>(p, Ys + threadIdx.x * LS, ts));
         }
+    } else if (p.rotated && p.kind != K_ROSENBROCK) {
+        if (threadIdx.x < TM && s_id[threadIdx.x] >= 0) {
+            T s1 = T(0), s2 = T(0);
+            for (int nt = 0; nt < p.Nt; ++nt) {
+                s1 += s_p1[threadIdx.x][nt];
+                s2 += s_p2[threadIdx.x][nt];
+            }
+            s_fnew[threadIdx.x] = p.kind == K_ACKLEY
+                                      ? T(-20) * exp(T(-0.2) * sqrt(s1 / T(D))) - exp(s2 / T(D)) +
+                                            T(20) + T(kE)
+                                      : s1;
+        }
     } else {
         for (int row = grp; row < TM; row += GROUPS) {
             T s1 = T(0), s2 = T(0);
             if (s_id[row] >= 0) {
                 for (int d = lane; d < D; d += G) {
-                    const T z = p.rotated ? Zs[row * LZ + d] : Ys[row * LS + d] - o[d];
+                    const T z = p.rotated ? Zs[row * LZ + d] : As[row * LS + d];
                     if (p.kind == K_ROSENBROCK) {
                         if (d + 1 < D) {
-                            const T zn = p.rotated ? Zs[row * LZ + d + 1] : Ys[row * LS + d + 1] - o[d + 1];
+                            const T zn = p.rotated ? Zs[row * LZ + d + 1] : As[row * LS + d + 1];
                             const T a = z + T(1), b = zn + T(1);
                             s1 += T(100) * (b - a * a) * (b - a * a) + (a - T(1)) * (a - T(1));
                         }
@@ -609,11 +786,11 @@ inline bool use_tile(const Params &p) {
 
 inline size_t tile_lds_bytes(const Params &p, bool fp64) {
     const size_t es = fp64 ? 8 : 4;
-    const size_t LS = (size_t)p.Dp + 1, LZ = (size_t)p.Nt * 16 + 1;
+    const size_t LS = (size_t)tile_row_stride(p, (int)es), LZ = (size_t)p.Nt * 16 + 1;
     size_t z = kTileRanks * LZ * es;
     const size_t ts = kTileRanks * ((size_t)p.dim + 1) * sizeof(int);
     if (ts > z) z = ts;
-    return 2 * kTileRanks * LS * es + z;
+    return 3 * kTileRanks * LS * es + z;
 }
 
 template <typename T, int NPMAX>
