@@ -57,6 +57,7 @@ def lib():
         L.oracle_bounded.argtypes = [C.c_uint32, C.c_uint32]
         L.oracle_subset_pi.restype = C.c_uint32
         L.oracle_subset_pi.argtypes = [C.c_uint32, C.c_uint32, P(C.c_uint32)]
+        L.oracle_subset_mask.argtypes = [C.c_uint32, C.c_uint32, P(C.c_uint32), P(C.c_uint8)]
         L.oracle_objective.restype = C.c_double
         L.oracle_objective.argtypes = [P(_Problem), P(C.c_double)]
         L.oracle_rank_order.argtypes = [C.c_int32, P(C.c_double), P(C.c_int32)]
@@ -100,6 +101,15 @@ def subset_pi(x: int, n: int, keys) -> int:
     k = np.ascontiguousarray(keys, dtype=np.uint32)
     assert k.shape == (8,)
     return lib().oracle_subset_pi(int(x), int(n), _ptr(k, C.c_uint32))
+
+
+def subset_mask(n: int, m: int, keys) -> list:
+    """Members (ascending) of the coordinate-mask m-subset of [0, n)."""
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    assert k.shape == (8,) and n >= 1
+    out = np.zeros(n, dtype=np.uint8)
+    lib().oracle_subset_mask(int(n), int(m), _ptr(k, C.c_uint32), _ptr(out, C.c_uint8))
+    return [int(x) for x in np.flatnonzero(out)]
 
 
 def rank_order(F) -> np.ndarray:

@@ -24,10 +24,12 @@
  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC'11), addressed by (purpose, block, index, iteration,
  * run) with the seed as key.  Exact m-subsets ("randperm(n, m)" in Eqs. (3),
- * (5) and Algorithm 1) are the elements x with pi(x) < m for a keyed
- * bijection pi of [0, n): an alternating Feistel network on ceil(log2 n)
- * bits with cycle walking (Black & Rogaway, "Ciphers with arbitrary finite
- * domains", CT-RSA 2002).
+ * (5) and Algorithm 1) come from a keyed alternating Feistel network on
+ * ceil(log2 n) bits.  The dormancy/reproduction set Dr holds the ranks x
+ * with pi(x) < m, pi being the network cycle-walked onto [0, n) (Black &
+ * Rogaway, "Ciphers with arbitrary finite domains", CT-RSA 2002), so one
+ * rank is tested on its own.  A coordinate mask holds the first m values
+ * below n met along the network's own order of the whole 2^b domain.
  *
  * Everything is IEEE binary64, evaluated in the order the formulas are
  * written; the file is compiled with -ffp-contract=off.
@@ -210,10 +212,35 @@ OR_EXPORT uint32_t oracle_subset_pi(uint32_t x, uint32_t n, const uint32_t keys[
     return y;
 }
 
-/* Is element x of [0, n) in the m-subset keyed by keys? */
+/* Is element x of [0, n) in the m-subset keyed by keys? (the set Dr) */
 static int in_subset(uint32_t x, uint32_t n, uint32_t m, const uint32_t keys[8])
 {
     return oracle_subset_pi(x, n, keys) < m;
+}
+
+/* The m-subset of the coordinates [0, n) for a mask (M_r of Eq. (3), M_f
+ * of Eq. (5)): walk v = 0, 1, ..., 2^b - 1, apply one pass of the network
+ * (no cycle walking) and keep the first m results below n.  Exactly m
+ * members; every m-subset is equally likely when the pass is a random
+ * permutation of [0, 2^b).  member[x] = 1 for members, 0 otherwise. */
+OR_EXPORT void oracle_subset_mask(uint32_t n, uint32_t m, const uint32_t keys[8],
+                                  uint8_t *member)
+{
+    uint32_t bits = 2;
+    while (bits < 32 && (1ull << bits) < (uint64_t)n)
+        ++bits;
+    uint32_t rounds = feistel_rounds(bits);
+    uint32_t k[24];
+    feistel_keys(keys, k, rounds);
+    memset(member, 0, n);
+    uint32_t taken = 0;
+    for (uint64_t v = 0; v < (1ull << bits) && taken < m; ++v) {
+        uint32_t y = feistel_once((uint32_t)v, bits, k, rounds);
+        if (y < n) {
+            member[y] = 1;
+            ++taken;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -472,6 +499,7 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
 
     double *Y = (double *)malloc(sizeof(double) * (size_t)ps * D);
     double *acc = (double *)malloc(sizeof(double) * (size_t)D);
+    uint8_t *mask = (uint8_t *)malloc((size_t)D);
 
     for (int r = 0; r < ps; ++r) {
         const int id = perm[r];
@@ -512,8 +540,9 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
                 double u_mr = oracle_uniform(draw_word(p, TAG_RANK, 3, 0, (uint32_t)r,
                                                        (uint32_t)t));
                 m = (int)ceil((double)D * u_mr);
+                oracle_subset_mask((uint32_t)D, (uint32_t)m, mkeys, mask);
                 for (int d = 0; d < D; ++d) {
-                    if (in_subset((uint32_t)d, (uint32_t)D, (uint32_t)m, mkeys)) {
+                    if (mask[d]) {
                         double U = oracle_uniform(draw_word(p, TAG_ELEM, 0, (uint32_t)d,
                                                            (uint32_t)r, (uint32_t)t));
                         double R = p->lb[d] + U * (p->ub[d] - p->lb[d]);
@@ -527,6 +556,7 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
             /* foraging: Eq. (4) factor and Eq. (5) mask of ceil(D*i/ps) dims */
             const double fac = u_f * f_scale;
             m = (int)ceil((double)D * (double)i / (double)ps);
+            oracle_subset_mask((uint32_t)D, (uint32_t)m, mkeys, mask);
             for (int d = 0; d < D; ++d)
                 acc[d] = 0.0;
             if (p_ah > u_op) {
@@ -557,7 +587,7 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
                 }
                 const double *xj = &X[(size_t)perm[j] * D];
                 for (int d = 0; d < D; ++d) {
-                    if (in_subset((uint32_t)d, (uint32_t)D, (uint32_t)m, mkeys))
+                    if (mask[d])
                         y[d] = xi[d] + fac * ((xj[d] - xi[d]) + acc[d] / (double)np);
                     else
                         y[d] = xi[d];
@@ -579,7 +609,7 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
                         acc[d] = acc[d] + wh * (X[(size_t)ida * D + d] - X[(size_t)idb * D + d]);
                 }
                 for (int d = 0; d < D; ++d) {
-                    if (in_subset((uint32_t)d, (uint32_t)D, (uint32_t)m, mkeys)) {
+                    if (mask[d]) {
                         double U = oracle_uniform(draw_word(p, TAG_ELEM, 0, (uint32_t)d,
                                                            (uint32_t)r, (uint32_t)t));
                         double xnear = (1.0 + (sgn * U) * near_scale) * xi[d];
@@ -608,6 +638,7 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
     }
     free(Fy);
     free(acc);
+    free(mask);
     free(Y);
     free(perm);
     return 0;

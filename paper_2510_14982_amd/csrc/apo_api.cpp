@@ -25,7 +25,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Offsets of every device array inside the workspace (bytes, 256-aligned).
 struct Layout {
-    size_t X[2], F, perm, Fs, ctrl, p_ah, fscale, cnear, p_dr, lb, ub, shift, rotp, htab, hist,
+    size_t X[2], F, perm, Fs, drf, ctrl, p_ah, fscale, cnear, p_dr, lb, ub, shift, rotp, htab, hist,
         best, trY, trF, trOp, total;
     int Dp, Nt, Ks;
 };
@@ -52,6 +52,7 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     L.F = take((size_t)pop * es);
     L.perm = take((size_t)pop * 4);
     L.Fs = take((size_t)pop * es);
+    L.drf = take((size_t)pop);
     L.ctrl = take(sizeof(Ctrl));
     L.p_ah = take((size_t)(o.max_iter + 1) * 8);
     L.fscale = take((size_t)(o.max_iter + 1) * 8);
@@ -261,6 +262,7 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     p.F = ws + L.F;
     p.perm = (int32_t *)(ws + L.perm);
     p.Fs = ws + L.Fs;
+    p.drf = (uint8_t *)(ws + L.drf);
     p.ctrl = (Ctrl *)(ws + L.ctrl);
     p.p_ah = (const double *)(ws + L.p_ah);
     p.fscale = (const double *)(ws + L.fscale);

@@ -67,14 +67,15 @@ __device__ __forceinline__ uint32_t bounded(uint32_t w, uint32_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Keyed bijection of [0, n): alternating Feistel network over
-// b = max(2, ceil(log2 n)) bits, cycle-walked back into [0, n).  The
-// element x belongs to the m-subset iff pi(x) < m, which gives exactly m
-// members with O(1) work per element and no shared state, so every lane
-// decides its own coordinates.  Round counts grow as the domain shrinks
-// (24, 20, 16, 12, 8 for b <= 4, 5-6, 7, 8-9, >= 10); for b <= 6 the round
-// function is a table held in the round key, above it is the top bits of
-// a 24 x 24-bit product.  Round keys 8.. are derived from keys 0..7.
+// Exact m-subsets of [0, n) from a keyed alternating Feistel network over
+// b = max(2, ceil(log2 n)) bits.  The set Dr of ranks is {x : pi(x) < m}
+// with pi the network cycle-walked back into [0, n), so a rank is tested
+// on its own with O(1) work; a coordinate mask is the first m values below
+// n along the network's order of [0, 2^b) (subset_mask_group).  Round
+// counts grow as the domain shrinks (24, 20, 16, 12, 8 for b <= 4, 5-6, 7,
+// 8-9, >= 10); for b <= 6 the round function is a table held in the round
+// key, above it is the top bits of a 24 x 24-bit product.  Round keys
+// 8 .. rounds - 1 are derived from keys 0..7.
 // ---------------------------------------------------------------------------
 struct Subset {
     uint32_t k[24];
@@ -106,14 +107,15 @@ __device__ __forceinline__ void subset_init(Subset &s, const uint32_t *keys8, ui
     for (int i = 8; i < 24; ++i) {
         uint32_t x = s.k[i - 8] ^ (s.k[i - 7] >> 16) ^ (uint32_t)i;
         x = x * 0x7FEB352Du;
-        s.k[i] = x ^ (x >> 15);
+        // only the keys of the rounds in use (the rest stay zero)
+        s.k[i] = i < (int)s.rounds ? x ^ (x >> 15) : 0u;
     }
 }
 
 // One round's function of the right half R (width c) into a bits.
 template <bool TABLE>
 __device__ __forceinline__ uint32_t feistel_f(uint32_t k, uint32_t R, uint32_t a, uint32_t c) {
-    if (TABLE) return (k >> (a * R)) & ((1u << a) - 1u);
+    if (TABLE) return (k >> (uint32_t)__umul24(a, R)) & ((1u << a) - 1u);   // a R < 32
     // HIP's __umul24 returns int: shift the product as unsigned
     return (uint32_t)__umul24((R << (24u - c)) ^ (k >> 8), (k & 0xFFFFFFu) | 1u) >> (32u - a);
 }
@@ -137,26 +139,6 @@ __device__ __forceinline__ uint32_t feistel_fwd(const uint32_t *k, uint32_t a0, 
     return (L << c0) | R;   // an even number of rounds restores the widths
 }
 
-// Inverse pass: forward round i maps (L, R) of widths (a, c) to
-// (R, L ^ f_i(R)) of widths (c, a); given (L', R') after round i,
-// R = L' and L = R' ^ f_i(L').
-template <int ROUNDS, bool TABLE>
-__device__ __forceinline__ uint32_t feistel_inv(const uint32_t *k, uint32_t a0, uint32_t c0,
-                                                uint32_t y) {
-    uint32_t L = y >> c0;
-    uint32_t R = y & ((1u << c0) - 1u);
-#pragma unroll
-    for (int i = ROUNDS - 1; i >= 0; --i) {
-        const uint32_t a = (i & 1) ? c0 : a0;   // left width before forward round i
-        const uint32_t c = (i & 1) ? a0 : c0;   // right width before forward round i
-        const uint32_t f = feistel_f<TABLE>(k[i], L, a, c);
-        const uint32_t prevR = L;
-        L = R ^ f;
-        R = prevR;
-    }
-    return (L << c0) | R;
-}
-
 // Round counts: 24 and 20 use the table function, 16, 12 and 8 the product.
 __device__ __forceinline__ uint32_t subset_pass(const Subset &s, uint32_t x) {
     switch (s.rounds) {
@@ -165,16 +147,6 @@ __device__ __forceinline__ uint32_t subset_pass(const Subset &s, uint32_t x) {
     case 16: return feistel_fwd<16, false>(s.k, s.a0, s.c0, x);
     case 12: return feistel_fwd<12, false>(s.k, s.a0, s.c0, x);
     default: return feistel_fwd<8, false>(s.k, s.a0, s.c0, x);
-    }
-}
-
-__device__ __forceinline__ uint32_t subset_pass_inv(const Subset &s, uint32_t y) {
-    switch (s.rounds) {
-    case 24: return feistel_inv<24, true>(s.k, s.a0, s.c0, y);
-    case 20: return feistel_inv<20, true>(s.k, s.a0, s.c0, y);
-    case 16: return feistel_inv<16, false>(s.k, s.a0, s.c0, y);
-    case 12: return feistel_inv<12, false>(s.k, s.a0, s.c0, y);
-    default: return feistel_inv<8, false>(s.k, s.a0, s.c0, y);
     }
 }
 
@@ -189,36 +161,41 @@ __device__ __forceinline__ uint32_t subset_pi(const Subset &s, uint32_t x) {
     return y;
 }
 
-// pi^-1 on [0, n): cycle walking through the inverse pass.
-__device__ __forceinline__ uint32_t subset_pi_inv(const Subset &s, uint32_t y) {
-    uint32_t x = y;
-    uint32_t steps = 0;
-    do {
-        x = subset_pass_inv(s, x);
-    } while (x >= s.n && ++steps < s.walk);
-    return x;
-}
-
-// The m-subset {x : pi(x) < m} = {pi^-1(i) : i < m} as a bitmask in LDS,
-// built by the G lanes of one group (all in one wavefront, all active).
-// Only min(m, n - m) inverse evaluations are needed: for m > n / 2 the
-// complement {pi^-1(i) : i >= m} is cleared from an all-ones mask.
+// The coordinate-mask m-subset as a bitmask in LDS: the first m values
+// below n along the pass order p(0), p(1), ..., p(2^b - 1) (one pass, no
+// cycle walking).  Built by the G lanes of one group (lanes lane0 ..
+// lane0 + G - 1 of one wavefront, all active): each round the lanes take
+// G consecutive positions, and a ballot gives each valid lane the number
+// of valid values before it, so the first m are kept without any lane
+// waiting on another.  For m > n / 2 the last n - m values (scanning from
+// the end) are cleared from an all-ones mask instead.
 template <int G>
 __device__ __forceinline__ void subset_mask_group(const Subset &s, uint32_t m, uint32_t *words,
-                                                  int nwords, int lane) {
-    const uint32_t n = s.n;
+                                                  int nwords, int lane, int lane0) {
+    const uint32_t n = s.n, dom = s.walk;
     const bool comp = m > n - m;
     const uint32_t cnt = comp ? n - m : m;
     for (int w = lane; w < nwords; w += G) words[w] = comp ? 0xFFFFFFFFu : 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (uint32_t idx = (uint32_t)lane; idx < cnt; idx += G) {
-        const uint32_t y = subset_pi_inv(s, comp ? m + idx : idx);
-        if (comp)
-            atomicAnd(&words[y >> 5], ~(1u << (y & 31)));
-        else
-            atomicOr(&words[y >> 5], 1u << (y & 31));
+    const uint64_t group = (G >= 64 ? ~0ull : ((1ull << G) - 1ull)) << lane0;
+    const uint64_t below = (1ull << (lane0 + lane)) - 1ull;   // lanes before this one
+    uint32_t taken = 0;
+    for (uint32_t base = 0; taken < cnt && base < dom; base += G) {
+        const uint32_t pos = base + (uint32_t)lane;
+        uint32_t y = 0xFFFFFFFFu;
+        if (pos < dom) y = subset_pass(s, comp ? dom - 1u - pos : pos);
+        const bool valid = y < n;
+        const uint64_t vb = __ballot(valid) & group;
+        const uint32_t before = (uint32_t)__popcll(vb & below);
+        if (valid && taken + before < cnt) {
+            if (comp)
+                atomicAnd(&words[y >> 5], ~(1u << (y & 31)));
+            else
+                atomicOr(&words[y >> 5], 1u << (y & 31));
+        }
+        taken += (uint32_t)__popcll(vb);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -278,13 +255,50 @@ __device__ __forceinline__ bool strictly_less(T a, T b) {
     return a < b;
 }
 
-// Butterfly sum over an aligned group of G lanes.  Each stage adds the same
-// two operands in every lane of a pair, so all lanes of the group end with
-// bit-identical totals.
+// A lane exchange applied to every 32-bit word of a value: DPP controls
+// within rows of 16 lanes, or a swizzle within 32.
+template <typename T>
+struct Words32 {
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    int w[sizeof(T) / 4];
+};
+template <int CTRL, typename T>
+__device__ __forceinline__ T lane_dpp(T v) {
+    Words32<T> a, b;
+    __builtin_memcpy(&a, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i)
+        b.w[i] = __builtin_amdgcn_update_dpp(0, a.w[i], CTRL, 0xF, 0xF, true);
+    T r;
+    __builtin_memcpy(&r, &b, sizeof(T));
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ T lane_swap16(T v) {   // lane l <-> l ^ 16
+    Words32<T> a, b;
+    __builtin_memcpy(&a, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i)
+        b.w[i] = __builtin_amdgcn_ds_swizzle(a.w[i], 0x401F);   // and 0x1F, xor 0x10
+    T r;
+    __builtin_memcpy(&r, &b, sizeof(T));
+    return r;
+}
+
+// Sum over an aligned group of G lanes (all active).  Stage by stage each
+// lane adds its value to that of a partner holding the same partial sum of
+// the other half of its block (quad xor 1 and xor 2, then the mirrors of 8
+// and 16 lanes, then xor 16 and xor 32), and the two lanes of a pair add
+// the same two operands, so every lane of the group ends with a
+// bit-identical total.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int s = 1; s < G; s <<= 1) v += __shfl_xor(v, s, 64);
+    if (G >= 2) v += lane_dpp<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+    if (G >= 4) v += lane_dpp<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+    if (G >= 8) v += lane_dpp<0x141>(v);    // row_half_mirror
+    if (G >= 16) v += lane_dpp<0x140>(v);   // row_mirror
+    if (G >= 32) v += lane_swap16(v);
+    if (G >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
 

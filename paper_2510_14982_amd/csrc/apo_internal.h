@@ -21,10 +21,9 @@ struct Ctrl {
     int32_t t_next;       // iteration being computed
     int32_t m_dr;         // |Dr| of iteration t_next
     int32_t best_id;      // written by the best kernel
-    uint32_t dr_keys[24]; // subset key schedule of Dr for iteration t_next
     double best_f;
     double p_ah, fscale, cnear;   // Eqs. (12), (4), (9) at t_next
-    int32_t pad[26];
+    int32_t pad[48];
 };
 
 // Everything a kernel needs, passed by value.  Element pointers are typed
@@ -43,6 +42,7 @@ struct Params {
     void *F;              // [pop] fitness by id (old values are read through Fs)
     int32_t *perm;        // [pop] rank -> id
     void *Fs;             // [pop] fitness in rank order (written with perm)
+    uint8_t *drf;         // [pop] 1 if rank r is in Dr this iteration (written with perm)
     Ctrl *ctrl;
     const double *p_ah;   // [max_iter + 1] Eq. (12)
     const double *fscale; // [max_iter + 1] 1 + cos(pi t / T) of Eq. (4)

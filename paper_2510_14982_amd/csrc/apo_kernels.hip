@@ -4,7 +4,8 @@
 //                 protozoa before it in the fitness order (ties by id),
 //                 counted in parallel over the whole population; then
 //                 perm[rank] = id.  Also opens the iteration: draws pf
-//                 (Eq. (11)) and the Dr subset keys (Algorithm 1).
+//                 (Eq. (11)) and the Dr subset keys (Algorithm 1) and
+//                 flags the ranks in Dr.
 //   (the step kernels themselves live in apo_step.hpp)
 //   best_kernel   argmin in the fitness order and a copy of that row.
 //   hist_kernel   256-bin histogram of an 8-bit image, per-wave LDS copies.
@@ -19,9 +20,11 @@ namespace apok {
 // registers (j = tid, tid + 256, ...), compares them against the 8 keys
 // being ranked (read by LDS broadcast) and keeps 8 counters, which are
 // summed over the workgroup by butterflies and LDS at the end.  No
-// workgroup depends on another.  Block 0 also opens the iteration: pf
-// (Eq. (11)), |Dr| and the Dr subset key schedule.  The sort also writes
-// the fitness in rank order (Fs), which the step reads instead of F.
+// workgroup depends on another.  Each workgroup also opens the iteration
+// (pf of Eq. (11), |Dr| and the Dr subset keys) and, for the ranks it
+// finds, writes the fitness in rank order (Fs, which the step reads instead
+// of F) and whether the rank is in Dr.  Workgroup 0 publishes the
+// iteration in the control block.
 // ---------------------------------------------------------------------------
 constexpr int kRankPer = 8;       // protozoa ranked per workgroup
 constexpr int kRankJ = 16;        // keys per thread per pass (256 x 16 = 4096 per pass)
@@ -43,12 +46,12 @@ struct RankKey<double> {  // 64-bit order key; equal keys fall back to the ids
     }
 };
 
-// Opens iteration t = ctrl.t + 1 (one wavefront): pf of Eq. (11), |Dr|, the
-// Dr subset key schedule and the iteration's schedule scalars.  Lanes 0-2
-// draw the three Philox blocks; lane 0 finishes.
-__device__ __forceinline__ void open_iteration(const Params &p) {
+// Opens iteration t (one wavefront, no memory reads): pf of Eq. (11), |Dr|
+// and the Dr subset key schedule into LDS.  Lanes 0-2 draw the three Philox
+// blocks; lane 0 finishes.
+__device__ __forceinline__ void open_iteration(const Params &p, int t, uint32_t *s_keys,
+                                               int32_t *s_mdr) {
     const int lane = threadIdx.x & 63;
-    const int t = p.ctrl->t + 1;
     const Stream rng = stream_of(p);
     const Words w = rng.block(TAG_ITER, (uint32_t)(lane < 3 ? lane : 0), 0, (uint32_t)t);
     const uint32_t u_pf = __shfl(w.w[0], 0, 64);
@@ -61,15 +64,12 @@ __device__ __forceinline__ void open_iteration(const Params &p) {
     if (lane == 0) {
         const int ps = p.pop;
         const double pf = p.pf_max * uniform<double>(u_pf);             // Eq. (11)
-        p.ctrl->m_dr = (int32_t)ceil((double)ps * pf);                    // |Dr|
+        const int32_t m_dr = (int32_t)ceil((double)ps * pf);              // |Dr|
         Subset drs;
         subset_init(drs, k8, (uint32_t)ps);
 #pragma unroll
-        for (int q = 0; q < 24; ++q) p.ctrl->dr_keys[q] = drs.k[q];
-        p.ctrl->p_ah = p.p_ah[t];
-        p.ctrl->fscale = p.fscale[t];
-        p.ctrl->cnear = p.cnear[t];
-        p.ctrl->t_next = t;
+        for (int q = 0; q < 24; ++q) s_keys[q] = drs.k[q];
+        *s_mdr = m_dr;
     }
 }
 
@@ -77,12 +77,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void rank_kernel(Params p) {
     __shared__ uint64_t s_ki[kRankPer];
     __shared__ int32_t part[4][kRankPer];
+    __shared__ uint32_t s_keys[24];
+    __shared__ int32_t s_mdr;
     const T *F = (const T *)p.F;
     const int ps = p.pop;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i0 = blockIdx.x * kRankPer;
-
-    if (blockIdx.x == 0 && tid < 64) open_iteration(p);
+    const int t = p.ctrl->t + 1;   // the iteration this sort opens
 
     if (tid < kRankPer) {
         const T fi = F[i0 + tid < ps ? i0 + tid : ps - 1];
@@ -106,6 +107,8 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
             const int j = base + 256 * u + tid;
             fj[u] = F[j < ps ? j : ps - 1];
         }
+        // the last wavefront opens the iteration while its loads are in flight
+        if (base == 0 && wave == 3) open_iteration(p, t, s_keys, &s_mdr);
         uint64_t kj[kRankJ];
 #pragma unroll
         for (int u = 0; u < kRankJ; ++u) {
@@ -134,6 +137,19 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
         const int rank = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
         p.perm[rank] = i0 + tid;
         ((T *)p.Fs)[rank] = F[i0 + tid];
+        // Dr of Algorithm 1: rank r belongs iff pi(r) < |Dr|
+        Subset drs;
+        subset_shape(drs, (uint32_t)ps);
+#pragma unroll
+        for (int q = 0; q < 24; ++q) drs.k[q] = s_keys[q];
+        p.drf[rank] = subset_has(drs, (uint32_t)rank, (uint32_t)s_mdr) ? 1 : 0;
+    }
+    if (blockIdx.x == 0 && tid == 64) {   // publish the iteration for the step
+        p.ctrl->m_dr = s_mdr;
+        p.ctrl->p_ah = p.p_ah[t];
+        p.ctrl->fscale = p.fscale[t];
+        p.ctrl->cnear = p.cnear[t];
+        p.ctrl->t_next = t;
     }
 }
 

@@ -53,6 +53,28 @@ __device__ __forceinline__ Stream stream_of(const Params &p) {
     return s;
 }
 
+// The open iteration's number and schedule scalars (Eqs. (4), (9), (12)),
+// published by the sort in the control block; read once at kernel entry.
+struct Iter {
+    int t;
+    double p_ah, fscale, cnear;
+};
+
+__device__ __forceinline__ Iter load_iter(const Params &p, int init) {
+    Iter it;
+    if (init) {
+        it.t = 0;
+        it.p_ah = it.fscale = it.cnear = 0.0;
+    } else {
+        const Ctrl *c = p.ctrl;
+        it.t = c->t_next;
+        it.p_ah = c->p_ah;
+        it.fscale = c->fscale;
+        it.cnear = c->cnear;
+    }
+    return it;
+}
+
 // ---------------------------------------------------------------------------
 // Per-protozoan plan of one iteration: which operation, its mask, scalars
 // and neighbours.  Every lane of the protozoan's group computes the same
@@ -87,6 +109,7 @@ template <typename T>
 struct Draws {
     Words s0, k1, k2, q3;
     double p_dr;
+    bool in_dr;                    // rank in Dr (flagged by the sort)
     int32_t idj, ida[2], idb[2];   // [0] autotroph pair, [1] heterotroph pair
     T fa[2], fb[2];
 };
@@ -104,6 +127,7 @@ __device__ __forceinline__ void plan_draws(const Params &p, int r, int t, int la
     c.id = p.perm[r];
     c.fold = Fs[r];
     d.p_dr = p.p_dr[r];
+    d.in_dr = p.drf[r] != 0;
     const Words mine = rng.block(TAG_RANK, (uint32_t)(lane & 3), (uint32_t)r, (uint32_t)t);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -129,15 +153,15 @@ __device__ __forceinline__ void plan_draws(const Params &p, int r, int t, int la
     d.fb[1] = Fs[b];
 }
 
-// The decisions of Algorithm 1 for rank r: Dr membership, the operation
-// (Eqs. (12), (13)), the mask size, the scalars and the neighbour pairs.
+// The decisions of Algorithm 1 for rank r that need only the draws: Dr
+// membership, the operation (Eqs. (12), (13)), the mask size and keys and
+// the scalars.  The neighbour pairs follow in plan_pairs, once the loaded
+// ids and fitness have arrived.
 template <typename T, int NPMAX>
-__device__ __forceinline__ void plan_decide(const Params &p, int r, int t, const Draws<T> &d,
-                                            Plan<T, NPMAX> &c) {
-    const Stream rng = stream_of(p);
+__device__ __forceinline__ void plan_decide(const Params &p, int r, const Iter &it,
+                                            const Draws<T> &d, Plan<T, NPMAX> &c) {
     const int ps = p.pop, D = p.dim;
-    const T *Fs = (const T *)p.Fs;
-    c.fac = T(0); c.srep = T(0); c.cn = T(p.ctrl->cnear); c.idj = 0;
+    c.fac = T(0); c.srep = T(0); c.cn = T(it.cnear); c.idj = 0;
     const uint32_t keys[8] = {d.k1.w[0], d.k1.w[1], d.k1.w[2], d.k1.w[3],
                               d.k2.w[0], d.k2.w[1], d.k2.w[2], d.k2.w[3]};
     subset_init(c.mask, keys, (uint32_t)D);
@@ -147,20 +171,12 @@ __device__ __forceinline__ void plan_decide(const Params &p, int r, int t, const
     const double sgn = uniform<double>(d.s0.w[3]) < 0.5 ? 1.0 : -1.0;
     c.sgn = T(sgn);
 
-    bool in_dr;
-    {
-        Subset drs;
-        subset_shape(drs, (uint32_t)ps);
-#pragma unroll
-        for (int i = 0; i < 24; ++i) drs.k[i] = p.ctrl->dr_keys[i];
-        in_dr = subset_has(drs, (uint32_t)r, (uint32_t)p.ctrl->m_dr);
-    }
 #pragma unroll
     for (int k = 0; k < NPMAX; ++k) {
         c.idm[k] = c.idp[k] = 0;
         c.w[k] = T(0);
     }
-    if (in_dr) {
+    if (d.in_dr) {
         if (d.p_dr > u_op) {                          // Eq. (13) -> dormancy
             c.op = OP_DORMANCY;
             c.m = (uint32_t)D;
@@ -172,10 +188,22 @@ __device__ __forceinline__ void plan_decide(const Params &p, int r, int t, const
         }
         return;
     }
-    c.fac = T(u_f * p.ctrl->fscale);
-    c.m = (uint32_t)(((uint64_t)D * (uint64_t)(r + 1) + (uint64_t)ps - 1ull) / (uint64_t)ps);
-    const bool autotroph = p.ctrl->p_ah > u_op;       // Eq. (12)
-    c.op = autotroph ? OP_AUTOTROPH : OP_HETEROTROPH;
+    c.fac = T(u_f * it.fscale);
+    // ceil(D (r + 1) / ps) in 32 bits: D <= 1024 and ps <= 65536
+    c.m = ((uint32_t)D * (uint32_t)(r + 1) + (uint32_t)ps - 1u) / (uint32_t)ps;
+    c.op = it.p_ah > u_op ? OP_AUTOTROPH : OP_HETEROTROPH;   // Eq. (12)
+}
+
+// Neighbour ids and weights of a foraging protozoan: X_j and the pairs of
+// Eq. (6) (autotroph) or Eq. (8) (heterotroph), weights of Eqs. (7), (10).
+template <typename T, int NPMAX>
+__device__ __forceinline__ void plan_pairs(const Params &p, int r, int t, const Draws<T> &d,
+                                           Plan<T, NPMAX> &c) {
+    if (c.op < OP_AUTOTROPH) return;
+    const Stream rng = stream_of(p);
+    const int ps = p.pop;
+    const T *Fs = (const T *)p.Fs;
+    const bool autotroph = c.op == OP_AUTOTROPH;
     c.idj = d.idj;
     c.idm[0] = autotroph ? d.ida[0] : d.ida[1];
     c.idp[0] = autotroph ? d.idb[0] : d.idb[1];
@@ -208,7 +236,8 @@ __device__ __forceinline__ void plan_mask(const Params &p, Plan<T, NPMAX> &c, ui
                                           int lane) {
     c.mw = mwords;
     if (c.op != OP_DORMANCY)
-        subset_mask_group<G>(c.mask, c.m, mwords, (p.dim + 31) / 32, lane);
+        subset_mask_group<G>(c.mask, c.m, mwords, (p.dim + 31) / 32, lane,
+                             (int)(threadIdx.x & 63) & ~(G - 1));
 }
 
 // Rows a lane reads for its NCH chunks of 4 coordinates, loaded before the
@@ -351,7 +380,8 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     const int item = (blockIdx.x * 256 + threadIdx.x) / G;
     if (item >= p.pop) return;
     const int D = p.dim, Dp = p.Dp;
-    const int t = init ? 0 : p.ctrl->t_next;
+    const Iter it = load_iter(p, init);
+    const int t = it.t;
     const int src = (t + 1) & 1, dst = t & 1;
     const T *Xc = (const T *)p.X[src];
     const T *Fc = (const T *)p.Fs;   // old fitness, in rank order
@@ -367,10 +397,10 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     } else {
         Draws<T> d;
         plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
-        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, false, false, rw);
-        plan_decide<T, NPMAX>(p, item, t, d, c);
-        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, false, true, false, rw);
-        plan_mask<T, NPMAX, G>(p, c, mwords[threadIdx.x / G], lane);
+        plan_decide<T, NPMAX>(p, item, it, d, c);   // while the ids load
+        plan_pairs<T, NPMAX>(p, item, t, d, c);
+        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, false, rw);
+        plan_mask<T, NPMAX, G>(p, c, mwords[threadIdx.x / G], lane);   // while the rows load
     }
     (void)Fc;
 
@@ -551,7 +581,8 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     T *As = Xs + TM * LS;     // y - o, the matrix-core A operand
     T *Zs = As + TM * LS;     // z = M (y - o) when a coordinate's neighbour is needed
     __shared__ T s_p1[TM][32], s_p2[TM][32];   // per column-tile partial sums
-    const int t = init ? 0 : p.ctrl->t_next;
+    const Iter it = load_iter(p, init);
+    const int t = it.t;
     const int src = (t + 1) & 1, dst = t & 1;
     const T *Xc = (const T *)p.X[src];
     const T *Fc = (const T *)p.Fs;   // old fitness, in rank order
@@ -578,11 +609,9 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
         }
     }
 
-    // zero the padded k range of the A operand
-    for (int q = threadIdx.x; q < TM * (4 * p.Ks - D); q += NT) {
-        const int row = q / (4 * p.Ks - D), col = D + q % (4 * p.Ks - D);
-        As[row * LS + col] = T(0);
-    }
+    // zero the padded k range of the A operand (each group its rows)
+    for (int row = grp; row < TM; row += GROUPS)
+        for (int col = D + lane; col < 4 * p.Ks; col += G) As[row * LS + col] = T(0);
 
     // phase 1: candidates into LDS
     for (int row = grp; row < TM; row += GROUPS) {
@@ -595,9 +624,10 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
             } else {
                 Draws<T> d;
                 plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
+                plan_decide<T, NPMAX>(p, item, it, d, c);   // while the ids load
                 load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, true, rw);
-                plan_decide<T, NPMAX>(p, item, t, d, c);
-                plan_mask<T, NPMAX, G>(p, c, s_mwords[grp], lane);
+                plan_mask<T, NPMAX, G>(p, c, s_mwords[grp], lane);   // while the rows load
+                plan_pairs<T, NPMAX>(p, item, t, d, c);
             }
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {

@@ -7,8 +7,8 @@
 //   mode "pi":     lines "n x k0..k7"    -> pi(x)
 //   mode "philox": lines "c0 c1 c2 c3 k0 k1" -> 4 words
 //   mode "key32":  lines "<hex bits of a float>" -> order key
-//   mode "mask":   lines "n m k0..k7"    -> the members of the m-subset built
-//                  from inverse evaluations, ascending, space separated
+//   mode "mask":   lines "n m k0..k7"    -> the members of the coordinate-mask
+//                  m-subset, ascending, space separated
 //   mode "cospi":  lines "<hex bits of a float x>" -> hex bits of cos(pi x)
 #include <cmath>
 #include <cstdint>
@@ -26,6 +26,12 @@ static inline unsigned int __umulhi(unsigned int a, unsigned int b) {
 static inline unsigned int __float_as_uint(float f) { unsigned int u; std::memcpy(&u, &f, 4); return u; }
 static inline long long __double_as_longlong(double f) { long long u; std::memcpy(&u, &f, 8); return u; }
 template <class T> static inline T __shfl_xor(T v, int, int) { return v; }
+// one lane: the ballot is that lane's predicate in bit 0
+static inline unsigned long long __ballot(int pred) { return pred ? 1ull : 0ull; }
+static inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+// lane exchanges (unused with one lane)
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) (src)
+#define __builtin_amdgcn_ds_swizzle(src, pat) (src)
 // one "lane" runs the whole group loop on the host (G = 1)
 #define __builtin_amdgcn_fence(a, b) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
@@ -60,7 +66,7 @@ int main(int argc, char **argv) {
             apok::Subset s;
             apok::subset_init(s, k, n);
             const int nw = (int)((n + 31) / 32);
-            apok::subset_mask_group<1>(s, m, words, nw, 0);
+            apok::subset_mask_group<1>(s, m, words, nw, 0, 0);
             for (unsigned x = 0; x < n; ++x)
                 if ((words[x >> 5] >> (x & 31)) & 1u) std::printf("%u ", x);
             std::printf("\n");

@@ -48,9 +48,11 @@ def test_subset_pi_matches_oracle_for_every_element(harness):
     assert got == want
 
 
-def test_inverse_mask_equals_forward_subset(harness):
-    """The GPU builds each mask from min(m, n - m) inverse evaluations; the
-    set must be exactly the oracle's {x : pi(x) < m}."""
+def test_mask_builder_equals_oracle_mask(harness):
+    """The GPU builds each coordinate mask by scanning the pass order (from
+    the end, clearing, when m > n / 2); the set must be exactly the
+    oracle's mask subset, for every domain width and both scan directions
+    (one lane here; the GPU parity tests cover the ballot across lanes)."""
     rng = np.random.default_rng(9)
     lines, want = [], []
     for n in list(range(1, 140)) + [255, 256, 1000, 1024]:
@@ -59,7 +61,7 @@ def test_inverse_mask_equals_forward_subset(harness):
                 continue
             keys = rng.integers(0, 2**32, size=8, dtype=np.uint64)
             lines.append(f"{n} {m} " + " ".join(str(int(k)) for k in keys))
-            want.append([x for x in range(n) if O.subset_pi(x, n, keys) < m])
+            want.append(O.subset_mask(n, m, keys))
     got = [[int(v) for v in l.split()] for l in _run(harness, "mask", lines)[:len(lines)]]
     assert got == want
 

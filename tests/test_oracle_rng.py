@@ -104,13 +104,22 @@ def test_subset_pi_is_bijection(n):
         assert sorted(ys) == list(range(n))
 
 
-@pytest.mark.parametrize("n,m", [(10, 3), (100, 25), (32, 4), (7, 3), (1000, 333), (3, 1)])
-def test_subset_inclusion_uniform(n, m):
+def _select(kind, n, m, keys):
+    """The m-subset of [0, n): the Dr form {x : pi(x) < m} or the mask form."""
+    if kind == "dr":
+        return [x for x in range(n) if O.subset_pi(x, n, keys) < m]
+    return O.subset_mask(n, m, keys)
+
+
+@pytest.mark.parametrize("kind", ["dr", "mask"])
+@pytest.mark.parametrize("n,m", [(10, 3), (100, 25), (100, 80), (32, 4), (7, 3), (1000, 333),
+                                 (3, 1)])
+def test_subset_inclusion_uniform(kind, n, m):
     trials = 3000 if n <= 100 else 600
     cnt = np.zeros(n)
     for t in range(trials):
         keys = _keys(t, n, m)
-        sel = [x for x in range(n) if O.subset_pi(x, n, keys) < m]
+        sel = _select(kind, n, m, keys)
         assert len(sel) == m
         cnt[sel] += 1
     # inclusion counts of a uniform m-subset: hypergeometric margins; the
@@ -121,14 +130,32 @@ def test_subset_inclusion_uniform(n, m):
     assert p > 1e-4, (chi, p)
 
 
+@pytest.mark.parametrize("kind", ["dr", "mask"])
 @pytest.mark.parametrize("n,m", [(4, 2), (5, 2), (6, 3), (8, 1), (7, 3), (9, 4)])
-def test_subset_second_order_uniform(n, m):
+def test_subset_second_order_uniform(kind, n, m):
     subsets = {s: i for i, s in enumerate(itertools.combinations(range(n), m))}
     cnt = np.zeros(len(subsets))
     trials = 400 * len(subsets)
     for t in range(trials):
         keys = _keys(t, 7 * n + m)
-        sel = tuple(x for x in range(n) if O.subset_pi(x, n, keys) < m)
+        sel = tuple(_select(kind, n, m, keys))
         cnt[subsets[sel]] += 1
     p = stats.chisquare(cnt).pvalue
     assert p > 1e-4, (cnt, p)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 31, 64, 100, 129, 1000])
+def test_mask_subsets_are_exact_and_nested(n):
+    """A mask of size m has exactly m distinct members in [0, n); for fixed
+    keys the masks grow one element at a time (the first m of one order),
+    m = 0 selects nothing and m = n everything."""
+    for trial in range(3):
+        keys = _keys(n, trial, 11)
+        prev = set()
+        for m in range(n + 1):
+            sel = O.subset_mask(n, m, keys)
+            assert len(sel) == m and len(set(sel)) == m
+            assert all(0 <= x < n for x in sel)
+            assert prev <= set(sel)
+            prev = set(sel)
+        assert sorted(prev) == list(range(n))
