@@ -83,7 +83,9 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
     const int ps = p.pop;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i0 = blockIdx.x * kRankPer;
-    const int t = p.ctrl->t + 1;   // the iteration this sort opens
+    // the iteration this sort opens (a vector load: the key loads below are
+    // issued without waiting for it)
+    const int t = __hip_atomic_load(&p.ctrl->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
 
     if (tid < kRankPer) {
         const T fi = F[i0 + tid < ps ? i0 + tid : ps - 1];

@@ -54,7 +54,9 @@ __device__ __forceinline__ Stream stream_of(const Params &p) {
 }
 
 // The open iteration's number and schedule scalars (Eqs. (4), (9), (12)),
-// published by the sort in the control block; read once at kernel entry.
+// published by the sort in the control block; read once at kernel entry
+// with vector loads (relaxed atomics), whose in-order counters let the
+// loads that do not depend on t issue before the first wait on t.
 struct Iter {
     int t;
     double p_ah, fscale, cnear;
@@ -66,11 +68,11 @@ __device__ __forceinline__ Iter load_iter(const Params &p, int init) {
         it.t = 0;
         it.p_ah = it.fscale = it.cnear = 0.0;
     } else {
-        const Ctrl *c = p.ctrl;
-        it.t = c->t_next;
-        it.p_ah = c->p_ah;
-        it.fscale = c->fscale;
-        it.cnear = c->cnear;
+        Ctrl *c = p.ctrl;
+        it.t = __hip_atomic_load(&c->t_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        it.p_ah = __hip_atomic_load(&c->p_ah, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        it.fscale = __hip_atomic_load(&c->fscale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        it.cnear = __hip_atomic_load(&c->cnear, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return it;
 }
@@ -345,12 +347,16 @@ __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX>
             }
         }
         const T npd = T(p.np);
+        if (p.np > 1) {   // acc / np; with one pair the quotient is acc itself
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = acc[e] / npd;
+        }
         if (c.op == OP_AUTOTROPH) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 y[e] = x[e];
                 if ((mb >> e) & 1u)
-                    y[e] = x[e] + c.fac * ((xj[e] - x[e]) + acc[e] / npd);          // Eq. (6)
+                    y[e] = x[e] + c.fac * ((xj[e] - x[e]) + acc[e]);                // Eq. (6)
             }
         } else {
 #pragma unroll
@@ -358,7 +364,7 @@ __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX>
                 y[e] = x[e];
                 if ((mb >> e) & 1u) {
                     const T xnear = (T(1) + (c.sgn * U[e]) * c.cn) * x[e];         // Eq. (9)
-                    y[e] = x[e] + c.fac * ((xnear - x[e]) + acc[e] / npd);          // Eq. (8)
+                    y[e] = x[e] + c.fac * ((xnear - x[e]) + acc[e]);                // Eq. (8)
                 }
             }
         }
@@ -672,6 +678,9 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     __syncthreads();
 
     const bool thresholds = p.kind == K_KAPUR || p.kind == K_OTSU;
+    // separable objectives of a rotated problem are summed from the matrix
+    // core accumulators in phase 2
+    const bool separable = p.rotated && !thresholds && p.kind != K_ROSENBROCK;
     if (p.rotated) {
         // phase 2: Z = (Y - o) M^T on the matrix cores.  Fragment layout of
         // v_mfma 16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
@@ -726,7 +735,7 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
                         }
                     }
                     g1 = group_sum<16>(g1);
-                    g2 = group_sum<16>(g2);
+                    if (p.kind == K_ACKLEY) g2 = group_sum<16>(g2);
                     if ((l & 15) == 0) {
                         s_p1[mfma_out_row<T>(l, v)][nt] = g1;
                         s_p2[mfma_out_row<T>(l, v)][nt] = g2;
@@ -743,18 +752,9 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
             int *ts = (int *)Zs + threadIdx.x * (D + 1);
             s_fnew[threadIdx.x] = T(threshold_objective<T>(p, Ys + threadIdx.x * LS, ts));
         }
-    } else if (p.rotated && p.kind != K_ROSENBROCK) {
-        if (threadIdx.x < TM && s_id[threadIdx.x] >= 0) {
-            T s1 = T(0), s2 = T(0);
-            for (int nt = 0; nt < p.Nt; ++nt) {
-                s1 += s_p1[threadIdx.x][nt];
-                s2 += s_p2[threadIdx.x][nt];
-            }
-            s_fnew[threadIdx.x] = p.kind == K_ACKLEY
-                                      ? T(-20) * exp(T(-0.2) * sqrt(s1 / T(D))) - exp(s2 / T(D)) +
-                                            T(20) + T(kE)
-                                      : s1;
-        }
+    } else if (separable) {
+        // the row sums of the column-tile partials are taken in phase 4 by
+        // each row's own group (the partials are visible since phase 2)
     } else {
         for (int row = grp; row < TM; row += GROUPS) {
             T s1 = T(0), s2 = T(0);
@@ -785,18 +785,38 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
             }
         }
     }
-    __syncthreads();
+    if (!separable) __syncthreads();
 
     // phase 4: greedy selection and the double-buffered write
     if (!init && blockIdx.x == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
     for (int row = grp; row < TM; row += GROUPS) {
         const int id = s_id[row];
         if (id < 0) continue;
-        const T fnew = s_fnew[row];
+        T fnew;
+        if (separable) {
+            // the same sequential sum in every lane (broadcast LDS reads)
+            T s1 = T(0), s2 = T(0);
+            for (int nt = 0; nt < p.Nt; ++nt) s1 += s_p1[row][nt];
+            if (p.kind == K_ACKLEY)
+                for (int nt = 0; nt < p.Nt; ++nt) s2 += s_p2[row][nt];
+            fnew = p.kind == K_ACKLEY
+                       ? T(-20) * exp(T(-0.2) * sqrt(s1 / T(D))) - exp(s2 / T(D)) + T(20) + T(kE)
+                       : s1;
+        } else {
+            fnew = s_fnew[row];
+        }
         const bool accept = init || strictly_less(fnew, s_fold[row]);
         const T *srcrow = accept ? Ys + row * LS : Xs + row * LS;
         T *out = Xn + (size_t)id * Dp;
-        for (int d = lane; d < D; d += G) out[d] = srcrow[d];
+        for (int d0 = 4 * lane; d0 < D; d0 += 4 * G) {
+            if (d0 + 4 <= D) {
+                T v[4];
+                load4(srcrow + d0, v);
+                store4(out + d0, v);
+            } else {
+                for (int d = d0; d < D; ++d) out[d] = srcrow[d];
+            }
+        }
         if (lane == 0) Fn[id] = accept ? fnew : s_fold[row];
         if (p.trace && !init) {
             T *ty = (T *)p.trY + (size_t)id * Dp;
