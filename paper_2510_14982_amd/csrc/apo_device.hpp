@@ -209,27 +209,6 @@ __device__ __forceinline__ bool subset_has(const Subset &s, uint32_t x, uint32_t
     return subset_pi(s, x) < m;
 }
 
-// cos(pi x) in binary32: x = n + f with n the nearest integer and |f| <= 1/2,
-// cos(pi x) = (-1)^n cos(pi f), and cos(pi f) from its Taylor series in f^2
-// through the f^12 term (the first dropped term is below 7e-9 for
-// |f| <= 1/2), evaluated by Horner's rule with fused multiply-adds.
-__device__ __forceinline__ float cospi_f32(float x) {
-    const float n = rintf(x);
-    const float f = x - n;                               // exact
-    const float f2 = f * f;
-    float q = 1.92957431e-03f;                           //  pi^12 / 12!
-    q = __builtin_fmaf(q, f2, -2.58068914e-02f);         // -pi^10 / 10!
-    q = __builtin_fmaf(q, f2, 2.35330630e-01f);          //  pi^8 / 8!
-    q = __builtin_fmaf(q, f2, -1.33526277e+00f);         // -pi^6 / 6!
-    q = __builtin_fmaf(q, f2, 4.05871213e+00f);          //  pi^4 / 4!
-    q = __builtin_fmaf(q, f2, -4.93480220e+00f);         // -pi^2 / 2!
-    q = __builtin_fmaf(q, f2, 1.0f);
-    // n odd iff n/2 is not an integer (every binary32 integer of magnitude
-    // 2^24 or more is even, and n/2 is exact below that)
-    const float h = 0.5f * n;
-    return (h != rintf(h)) ? -q : q;
-}
-
 // ---------------------------------------------------------------------------
 // Fitness order: ascending, -0 == +0, every NaN after +inf, ties by id.
 // The order-preserving unsigned image of a float/double; NaN maps to the

@@ -40,10 +40,13 @@ __device__ __forceinline__ void store4(T *p, const T v[4]) {
     *reinterpret_cast<typename V4<T>::type *>(p) = q;
 }
 
-// cos(2 pi z): binary64 follows the textbook expression; binary32 uses
-// cospi_f32(2z): 2z is exact and the reduction to [-1/2, 1/2] is exact.
+// cos(2 pi z): binary64 follows the textbook expression; binary32 reduces z
+// exactly to [-1/2, 1/2] and uses the hardware cosine, which takes its
+// argument in revolutions (measured within 1.3e-7 of binary64 cos there).
 __device__ __forceinline__ double cos2pi(double z) { return cos(2.0 * kPi * z); }
-__device__ __forceinline__ float cos2pi(float z) { return apok::cospi_f32(2.0f * z); }
+__device__ __forceinline__ float cos2pi(float z) {
+    return __builtin_amdgcn_cosf(z - rintf(z));
+}
 
 __device__ __forceinline__ Stream stream_of(const Params &p) {
     Stream s;
@@ -153,6 +156,21 @@ __device__ __forceinline__ void plan_draws(const Params &p, int r, int t, int la
     d.fb[0] = Fs[kp];
     d.fa[1] = Fs[a];
     d.fb[1] = Fs[b];
+}
+
+// With one protozoan per wavefront its draws are wavefront-uniform: move
+// them to scalar registers (frees vector registers for the rows in flight).
+template <int G, typename T>
+__device__ __forceinline__ void uniform_draws(Draws<T> &d) {
+    if (G == 64) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            d.s0.w[e] = __builtin_amdgcn_readfirstlane(d.s0.w[e]);
+            d.k1.w[e] = __builtin_amdgcn_readfirstlane(d.k1.w[e]);
+            d.k2.w[e] = __builtin_amdgcn_readfirstlane(d.k2.w[e]);
+            d.q3.w[e] = __builtin_amdgcn_readfirstlane(d.q3.w[e]);
+        }
+    }
 }
 
 // The decisions of Algorithm 1 for rank r that need only the draws: Dr
@@ -403,6 +421,7 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     } else {
         Draws<T> d;
         plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
+        uniform_draws<G>(d);
         plan_decide<T, NPMAX>(p, item, it, d, c);   // while the ids load
         plan_pairs<T, NPMAX>(p, item, t, d, c);
         load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, false, rw);
@@ -413,7 +432,7 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     T xs[NCH][4], ys[NCH][4];
     const T *o = (const T *)p.shift;
     T s1 = T(0), s2 = T(0);
-    T zfirst[NCH], zs[NCH][4];
+    const bool separable = p.kind != K_ROSENBROCK;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
         const int d0 = 4 * (lane + ch * G);
@@ -422,18 +441,38 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
                                  rw.ap[ch], rw.am[ch], rw.ap[ch], ys[ch]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) xs[ch][e] = rw.x[ch][e];
-            T ov[4];
-            load4(o + d0, ov);
+            if (separable) {   // objective terms of this chunk right away
+                T ov[4];
+                load4(o + d0, ov);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) zs[ch][e] = ys[ch][e] - ov[e];
+                for (int e = 0; e < 4; ++e) {
+                    if (d0 + e < D) {
+                        const T z = ys[ch][e] - ov[e];
+                        if (p.kind == K_RASTRIGIN) {
+                            s1 += z * z - T(10) * cos2pi(z) + T(10);
+                        } else {
+                            s1 += z * z;
+                            if (p.kind == K_ACKLEY) s2 += cos2pi(z);
+                        }
+                    }
+                }
+            }
         } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) xs[ch][e] = ys[ch][e] = zs[ch][e] = T(0);
+            for (int e = 0; e < 4; ++e) xs[ch][e] = ys[ch][e] = T(0);
         }
-        zfirst[ch] = zs[ch][0];
     }
-    // objective
-    if (p.kind == K_ROSENBROCK) {
+    if (!separable) {   // Rosenbrock couples each coordinate with the next
+        T zfirst[NCH], zs[NCH][4];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int d0 = 4 * (lane + ch * G);
+            T ov[4] = {T(0), T(0), T(0), T(0)};
+            if (d0 < D) load4(o + d0, ov);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) zs[ch][e] = d0 < D ? ys[ch][e] - ov[e] : T(0);
+            zfirst[ch] = zs[ch][0];
+        }
         const int wl = threadIdx.x & 63;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
@@ -448,23 +487,6 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
                     const T a = zs[ch][e] + T(1);
                     const T b = (e < 3 ? zs[ch][e + 1] : after) + T(1);
                     s1 += T(100) * (b - a * a) * (b - a * a) + (a - T(1)) * (a - T(1));
-                }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int d0 = 4 * (lane + ch * G);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (d0 + e < D) {
-                    const T z = zs[ch][e];
-                    if (p.kind == K_RASTRIGIN) {
-                        s1 += z * z - T(10) * cos2pi(z) + T(10);
-                    } else {
-                        s1 += z * z;
-                        if (p.kind == K_ACKLEY) s2 += cos2pi(z);
-                    }
                 }
             }
         }

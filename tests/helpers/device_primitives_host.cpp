@@ -9,7 +9,6 @@
 //   mode "key32":  lines "<hex bits of a float>" -> order key
 //   mode "mask":   lines "n m k0..k7"    -> the members of the coordinate-mask
 //                  m-subset, ascending, space separated
-//   mode "cospi":  lines "<hex bits of a float x>" -> hex bits of cos(pi x)
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -70,15 +69,6 @@ int main(int argc, char **argv) {
             for (unsigned x = 0; x < n; ++x)
                 if ((words[x >> 5] >> (x & 31)) & 1u) std::printf("%u ", x);
             std::printf("\n");
-        }
-    } else if (!std::strcmp(mode, "cospi")) {
-        unsigned b;
-        while (std::scanf("%x", &b) == 1) {
-            float f;
-            std::memcpy(&f, &b, 4);
-            const float c = apok::cospi_f32(f);
-            std::memcpy(&b, &c, 4);
-            std::printf("%08x\n", b);
         }
     } else if (!std::strcmp(mode, "key32")) {
         unsigned b;
