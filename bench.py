@@ -101,6 +101,55 @@ def timed_run(torch, apo, w, precision, steps, warmup):
     return dt, best_f
 
 
+def repeat_runs(torch, apo, w, precision, runs=5):
+    """Whole runs of the configured length, each on a fresh handle (the
+    paper reports the average of 5 runs); evals/s of each."""
+    out = []
+    for _ in range(runs):
+        with make_handle(apo, w, precision) as g:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.run(w.max_iter)
+            torch.cuda.synchronize()
+            out.append(w.pop * w.max_iter / (time.perf_counter() - t0))
+    return out
+
+
+def measured_peaks(torch):
+    """What this device reaches on plain library work: a device-to-device
+    copy (read + write bytes) and large GEMMs through torch.matmul (the
+    vendor BLAS, run as a black box)."""
+    res = {}
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    res["copy_GB_per_s"] = 2 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    for name, dt, m in (("bf16", torch.bfloat16, 8192), ("fp32", torch.float32, 8192)):
+        x = torch.randn(m, m, device="cuda").to(dt)
+        y = torch.randn(m, m, device="cuda").to(dt)
+        for _ in range(3):
+            torch.matmul(x, y)
+        torch.cuda.synchronize()
+        e0.record()
+        reps = 20
+        for _ in range(reps):
+            torch.matmul(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        res[f"gemm_{name}_TFLOP_per_s"] = 2 * m ** 3 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    return res
+
+
 def kernel_times(apo, w, precision, iters):
     with make_handle(apo, w, precision) as g:
         n, kt = g.time_kernels(min(iters, w.max_iter))
@@ -123,6 +172,48 @@ def workload(name, seed):
     raise SystemExit(f"unknown workload {name}")
 
 
+# The paper's single-threshold Otsu timings (CUDA version, Tesla T4, 5-run
+# average, seconds; the image is rescanned per evaluation there): context.
+PAPER_OTSU_PAR_S = {512: 3.0, 1024: 13.0, 2048: 50.0, 4096: 199.0}
+
+
+def otsu_table(torch, apo, args):
+    """Histogram + 50 iterations of single-threshold Otsu (ps 100, D 1,
+    binary64) per synthetic image size; one JSON line."""
+    import gen
+    rows = {}
+    for side in (512, 1024, 2048, 4096):
+        w = gen.otsu_single(side=side, seed=args.seed)
+        img = torch.from_numpy(w.extra["image"]).cuda().reshape(-1)
+        apo.histogram_u8(img)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            h = apo.histogram_u8(img).cpu().numpy().astype("uint64")
+            with apo.APO(w.dim, w.lb, w.ub, w.pop, seed=w.seed, max_iter=w.max_iter,
+                         precision="fp64", kind=w.kind, hist=h) as g:
+                g.run(w.max_iter)
+                xb, fb, _ = g.best()
+            times.append(time.perf_counter() - t0)
+        assert (h == w.hist).all(), "GPU histogram differs from numpy's"
+        med = sorted(times)[2]
+        rows[f"{side}x{side}"] = {"seconds_median_of_5": med, "best_threshold": float(round(xb[0])),
+                                  "paper_cuda_seconds": PAPER_OTSU_PAR_S[side],
+                                  "evals_per_s": w.pop * w.max_iter / med}
+    big = rows["4096x4096"]
+    print(json.dumps({
+        "metric": "single-threshold Otsu: histogram + 50 APO iterations per image (ps 100, D 1)",
+        "value": big["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": 50, "warmup": 1,
+        "ms_per_step": 1000.0 * big["seconds_median_of_5"] / 50, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "otsu_k1_ps100_t50", "images": list(rows)},
+        "per_image": rows,
+        "note": "wall time per image includes the GPU histogram, handle creation, 50 iterations "
+                "and the best read-back; the paper's times are context only (other hardware, "
+                "image rescanned per evaluation)"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,12 +221,16 @@ def main():
                     help="timed iterations (default: the workload's configured run length)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "elem-large"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "elem-large", "otsu"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="also measure the device's copy bandwidth and library GEMM rates")
+    ap.add_argument("--no-repeats", action="store_true",
+                    help="skip the five whole-run repeats")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -155,6 +250,9 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": 5}))
         return
 
+    if args.workload == "otsu":
+        otsu_table(torch, apo, args)
+        return
     w, precision = workload(args.workload, args.seed)
     steps = w.max_iter if args.steps is None else args.steps
     es = 8 if precision == "fp64" else 4
@@ -179,6 +277,12 @@ def main():
                               "hbm_frac": img.numel() / (hist_us * 1e-6) / 1e9 / PEAK_HBM_GBS}
     dt, best_f = timed_run(torch, apo, w, precision, steps, args.warmup)
     kn, kt = kernel_times(apo, w, precision, args.kernel_iters)
+    if not args.no_repeats:
+        reps = repeat_runs(torch, apo, w, precision)
+        extra["runs_evals_per_s"] = {"runs": reps, "median": sorted(reps)[len(reps) // 2],
+                                     "iterations_each": w.max_iter}
+    if args.peaks:
+        extra["measured_peaks"] = measured_peaks(torch)
     step_us = kt["step_us"]
     bytes_alg = 2.0 * w.pop * w.dim * es          # read X once, write X' once
     out = {

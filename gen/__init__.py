@@ -152,6 +152,19 @@ def kapur_thresholds(k: int = 4, seed: int = 1, side: int = 4096, pop: int = 102
     return w
 
 
+def otsu_single(side: int = 512, seed: int = 1, pop: int = 100, max_iter: int = 50,
+                precision: str = "fp64", img: Optional[np.ndarray] = None) -> Workload:
+    """Single-threshold Otsu in the shape of the paper's thresholding table:
+    ps 100, D 1, 50 iterations, bounds [0, 255], on a synthetic side x side
+    blob image (standing in for the paper's colour test image)."""
+    if img is None:
+        img = blob_image(side, side, seed)
+    w = Workload(f"otsu_k1_img{side}_ps{pop}_{precision}", 1, pop, max_iter, precision, "otsu",
+                 np.zeros(1), np.full(1, 255.0), seed=seed, hist=histogram_of(img))
+    w.extra["image"] = img
+    return w
+
+
 WORKLOADS = {
     "c1": shifted_rastrigin_small,
     "c2": rotated_rastrigin_large,

@@ -130,6 +130,39 @@ def test_c1_full_run_matches_oracle():
         assert abs(fb - Fo[b]) <= 1e-9 * max(1.0, abs(Fo[b]))
 
 
+def test_otsu_single_threshold_run_matches_oracle():
+    """The thresholding application in the paper's table shape: one Otsu
+    threshold, ps 100, D 1, 50 binary64 iterations from the GPU's own
+    initialisation, on a 512 x 512 synthetic image.  Thresholds (rint of
+    the coordinate) agree exactly at every checkpoint and the fitness to
+    the prefix-table rounding; the final best threshold is the oracle's."""
+    apo = need_gpu()
+    import torch
+    print("[run] otsu ps100 D1 T50 fp64", flush=True)
+    w = gen.otsu_single(side=512, seed=4)
+    img = torch.from_numpy(w.extra["image"]).cuda().reshape(-1)
+    h = apo.histogram_u8(img).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(h, w.hist)
+    with apo.APO(w.dim, w.lb, w.ub, w.pop, seed=w.seed, max_iter=w.max_iter, precision="fp64",
+                 kind=w.kind, hist=h) as g:
+        p = O.Problem(dim=w.dim, pop=w.pop, lb=w.lb, ub=w.ub, max_iter=w.max_iter, seed=w.seed,
+                      kind=w.kind, hist=w.hist)
+        Xo, Fo = p.init()
+        t = 0
+        while t < w.max_iter:
+            n = g.run(10)
+            Xo, Fo, t2 = p.run(Xo, Fo, t, n)
+            t += n
+            X, F, tg = g.get_state()
+            assert tg == t == t2
+            assert np.array_equal(np.rint(X), np.rint(Xo)), t
+            assert np.allclose(F, Fo, rtol=1e-9, atol=1e-12), t
+        xb, fb, _ = g.best()
+        b = O.best(Fo)
+        assert np.rint(xb[0]) == np.rint(Xo[b][0])
+        assert abs(fb - Fo[b]) <= 1e-9 * max(1.0, abs(Fo[b]))
+
+
 def test_graph_replay_equals_single_steps_and_is_deterministic():
     apo = need_gpu()
     print("[run] graph replay vs steps", flush=True)
