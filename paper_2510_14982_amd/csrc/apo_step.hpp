@@ -544,46 +544,54 @@ __device__ __forceinline__ int mfma_out_row<float>(int l, int v) { return 4 * (l
 template <>
 __device__ __forceinline__ int mfma_out_row<double>(int l, int v) { return 4 * v + (l >> 4); }
 
+// Thresholding objectives (Kapur entropy, Otsu between-class variance) of
+// one candidate, by a team of 32 lanes of one wavefront.  Thresholds are
+// the coordinates rounded half to even; each is placed at its position in
+// ascending order by counting (ties keep coordinate order), so class c is
+// the grey levels [t_(c-1), t_c) with t_(-1) = 0 and t_k = 256.  Class
+// weights and moments are differences of the binary64 prefix tables
+// P (probability), S (p ln p) and M1 (level x probability); empty classes
+// add nothing.  Each lane adds its classes; the team total is the same in
+// every lane.  F is minus the criterion.
 template <typename T>
-__device__ __forceinline__ double threshold_objective(const Params &p, const T *yrow, int *ts) {
+__device__ __forceinline__ double threshold_objective_team(const Params &p, const T *yrow,
+                                                           int *ts, int tl, bool live) {
     const int k = p.dim;
-    for (int c = 0; c < k; ++c) {
-        // round half to even, then insertion into the sorted prefix
-        int v = (int)rint((double)yrow[c]);
-        int j = c;
-        while (j > 0 && ts[j - 1] > v) {
-            ts[j] = ts[j - 1];
-            --j;
+    if (live) {
+        for (int c = tl; c < k; c += 32) {
+            const int v = (int)rint((double)yrow[c]);
+            int pos = 0;
+            for (int q = 0; q < k; ++q) {
+                const int u = (int)rint((double)yrow[q]);
+                pos += (u < v || (u == v && q < c)) ? 1 : 0;
+            }
+            ts[pos] = v;
         }
-        ts[j] = v;
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double *P = p.htab, *S = p.htab + 257, *M1 = p.htab + 514;
-    double total = 0.0;
-    int a = 0;
-    if (p.kind == K_KAPUR) {
-        for (int c = 0; c <= k; ++c) {
+    const double muT = M1[256];
+    double part = 0.0;
+    if (live) {
+        for (int c = tl; c <= k; c += 32) {
+            const int a = c == 0 ? 0 : ts[c - 1];
             const int b = c < k ? ts[c] : 256;
             const double omega = P[b] - P[a];
-            if (omega > 0.0) total += log(omega) - (S[b] - S[a]) / omega;
-            a = b;
+            if (omega > 0.0) {
+                if (p.kind == K_KAPUR) {
+                    part += log(omega) - (S[b] - S[a]) / omega;
+                } else {
+                    const double mu = (M1[b] - M1[a]) / omega;
+                    part += omega * (mu - muT) * (mu - muT);
+                }
+            }
         }
-        return -total;
     }
-    const double muT = M1[256];
-    for (int c = 0; c <= k; ++c) {
-        const int b = c < k ? ts[c] : 256;
-        const double omega = P[b] - P[a];
-        if (omega > 0.0) {
-            const double mu = (M1[b] - M1[a]) / omega;
-            total += omega * (mu - muT) * (mu - muT);
-        }
-        a = b;
-    }
-    return -total;
+    return -group_sum<32>(part);
 }
 
-// LDS row stride of the tile: room for the padded k range of the A operand,
-// odd so the 16 rows of an A fragment fall in different banks.
 // LDS row stride (elements) of the tile's row buffers.  The matrix-core A
 // operand is read as 16-byte vectors by 16 lanes of 16 different rows at a
 // time; a stride of 4 words (mod 64) puts those rows in 16 distinct groups
@@ -598,6 +606,7 @@ __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
 template <typename T, int G, int NCH, int NPMAX>
 __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     constexpr int NT = 512, TM = kTileRanks, GROUPS = NT / G;
+    static_assert(NT / 32 == TM, "one 32-lane team per row in the thresholding phase");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_id[TM], s_op[TM];
     __shared__ uint32_t s_mwords[GROUPS][(4 * G * NCH + 31) / 32];
@@ -770,10 +779,12 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
 
     // phase 3: objective per protozoan
     if (thresholds) {
-        if (threadIdx.x < TM && s_id[threadIdx.x] >= 0) {
-            int *ts = (int *)Zs + threadIdx.x * (D + 1);
-            s_fnew[threadIdx.x] = T(threshold_objective<T>(p, Ys + threadIdx.x * LS, ts));
-        }
+        // one 32-lane team per row (the 512 threads are 16 teams)
+        const int row = threadIdx.x >> 5, tl = threadIdx.x & 31;
+        const bool live = s_id[row] >= 0;
+        int *ts = (int *)Zs + row * (D + 1);
+        const double f = threshold_objective_team<T>(p, Ys + row * LS, ts, tl, live);
+        if (tl == 0 && live) s_fnew[row] = T(f);
     } else if (separable) {
         // the row sums of the column-tile partials are taken in phase 4 by
         // each row's own group (the partials are visible since phase 2)
