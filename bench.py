@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_tile_f32_rotated_rastrigin_ps4096_d100_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tile_f32_rotated_rastrigin_ps4096_d100.md")
 KERNEL_SOURCES = ["apo_step.hpp", "apo_device.hpp", "apo_step_tile_f32.hip"]
 
 
@@ -40,14 +40,21 @@ def kernel_source_hash() -> str:
 def measured_traffic():
     """HBM bytes per launch of the step kernel from the committed counter
     summary, only if it was taken on the current kernel source."""
+    fields = {}
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            for line in f:
+                if ":" in line and not line.startswith((" ", "|", "#")):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+    except OSError:
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if fields.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return t.get("hbm_bytes_per_launch")
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, budget_s: float):
