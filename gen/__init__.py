@@ -165,6 +165,29 @@ def otsu_single(side: int = 512, seed: int = 1, pop: int = 100, max_iter: int = 
     return w
 
 
+def batched_runs(n: int = 512, seed: int = 1, max_iter: int = 1000,
+                 dims=(10, 20, 50, 100), pops=(64, 256, 1024),
+                 kinds=("rastrigin", "rosenbrock", "ackley")) -> list:
+    """Independent FP32 runs for the batched form: a balanced, seeded
+    shuffle of dims x pops x kinds (each combination n // combos or one
+    more times), every run shifted and rotated with its own o ~ U[-80, 80]
+    and Haar M, bounds [-100, 100], np 1, pf_max 0.1, seed seed + i and
+    run id i.  Returns a list of Workload."""
+    combos = [(d, p, k) for d in dims for p in pops for k in kinds]
+    reps = [n // len(combos) + (1 if i < n % len(combos) else 0) for i in range(len(combos))]
+    plan = [c for c, r in zip(combos, reps) for _ in range(r)]
+    order = np.random.default_rng(seed).permutation(len(plan))
+    out = []
+    for i, j in enumerate(order):
+        d, p, k = plan[j]
+        s = seed * 100003 + i
+        w = Workload(f"batch_{i}_{k}_d{d}_ps{p}", d, p, max_iter, "fp32", k,
+                     np.full(d, -100.0), np.full(d, 100.0), seed=seed + i, run=i,
+                     shift=shift_vector(d, s), rot=rotation_matrix(d, s))
+        out.append(w)
+    return out
+
+
 WORKLOADS = {
     "c1": shifted_rastrigin_small,
     "c2": rotated_rastrigin_large,

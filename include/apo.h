@@ -168,6 +168,71 @@ int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint32_t *d_hist, void *s
 /* Static description of a status code. */
 const char *apo_strerror(int status);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent runs.  Many runs of Algorithm 1, each with its own
+ * dimension, population, objective, seed and budget, advance together:
+ * every iteration is one sort launch per precision and one step launch per
+ * kernel shape covering all runs (workgroups are mapped to (run, block)
+ * through a device table), replayed from captured graphs.  Each run
+ * computes exactly what a standalone handle with the same arguments
+ * computes (same kernels, same draws, same arithmetic).
+ * ------------------------------------------------------------------------ */
+typedef struct apo_batch apo_batch_t;   /* opaque, owned by the caller until apo_batch_destroy */
+
+typedef struct {
+    int32_t dim;
+    const double *lb, *ub;   /* host [dim], copied                                   */
+    int32_t pop;
+    int32_t np;
+    double pf_max;
+    uint64_t seed;
+    apo_options opt;         /* max_iter, precision, objective, run_id, flags; its
+                                stream and workspace must be NULL / 0 (the batch
+                                supplies both)                                      */
+} apo_run_desc;
+
+typedef struct {
+    void *stream;            /* hipStream_t, or NULL = library-owned stream          */
+    void *workspace;         /* device buffer of apo_batch_workspace_bytes, or NULL  */
+    size_t workspace_bytes;
+} apo_batch_options;
+
+/* Device bytes a batch of these runs needs (0 if any description is
+ * invalid): every run's own workspace plus the launch tables. */
+size_t apo_batch_workspace_bytes(int32_t n, const apo_run_desc *runs);
+
+/* Creates n >= 1 runs and their initial populations.  Errors: those of
+ * apo_create for the first failing run (nothing is left allocated),
+ * APO_E_INVAL for n < 1, a run description with a stream or workspace, or
+ * a workspace that is too small. */
+int apo_batch_create(int32_t n, const apo_run_desc *runs, const apo_batch_options *opt,
+                     apo_batch_t **out);
+
+/* Advances every run by min(iters, the smallest remaining budget)
+ * iterations, asynchronously on the batch stream.  Returns that count
+ * (>= 0) or a status; APO_E_STATE if the runs are not all at the same
+ * iteration (after apo_set_state on a member). */
+int apo_batch_run(apo_batch_t *b, int32_t iters);
+
+/* View of run i (0 <= i < n) as a handle owned by the batch: apo_best,
+ * apo_info, apo_get_state, apo_set_state and apo_get_trace work on it;
+ * apo_step, apo_run, apo_time_kernels and apo_destroy return APO_E_STATE. */
+int apo_batch_member(apo_batch_t *b, int32_t i, apo_t **run);
+
+/* Launch-schedule autotuner: times `iters` iterations (clipped to the
+ * smallest remaining budget; at least 1) under each candidate schedule --
+ * step launches in sequence or on parallel graph branches, workgroups in
+ * run order or interleaved across runs -- restoring the runs' state after
+ * every trial, and keeps the fastest.  Results do not depend on the
+ * schedule.  Allocates a temporary device copy of the runs' state.
+ * *schedule (may be NULL) receives the chosen schedule (0..3), *us (may be
+ * NULL) four timings in microseconds per iteration. */
+int apo_batch_tune(apo_batch_t *b, int32_t iters, int32_t *schedule, double *us);
+
+/* Releases the batch, its members and (if library-allocated) its stream
+ * and workspace after the batch stream drains. */
+int apo_batch_destroy(apo_batch_t *b);
+
 #ifdef __cplusplus
 }
 #endif

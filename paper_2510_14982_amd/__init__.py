@@ -5,7 +5,9 @@ initial population), ``step`` / ``run`` (the per-iteration population step:
 sort, Dr, Eqs. (1)-(13), clamp, evaluation, greedy selection), ``best``
 (Algorithm 1's output), checkpoint/trace hooks and per-kernel timing.
 ``histogram_u8`` reduces an 8-bit image on the GPU for the thresholding
-objectives.  PyTorch provides the device workspace and the stream.
+objectives.  ``Batch`` advances many independent runs together (one launch
+per kernel shape per iteration) and hands out each run as a non-owning
+``APO`` view.  PyTorch provides the device workspace and the stream.
 """
 from __future__ import annotations
 
@@ -15,9 +17,10 @@ from typing import Optional
 import numpy as np
 
 from ._lib import (APO_E_DONE, APO_FLAG_TRACE, APO_FP32, APO_FP64, KINDS, OPS, APOError,
-                   Objective, Options, _check, _dptr, lib, strerror)
+                   BatchOptions, Objective, Options, RunDesc, _check, _dptr, lib, strerror)
 
-__all__ = ["APO", "APOError", "histogram_u8", "workspace_bytes", "lib", "strerror", "OPS"]
+__all__ = ["APO", "APOError", "Batch", "histogram_u8", "workspace_bytes", "lib", "strerror",
+           "OPS"]
 
 
 def _torch():
@@ -90,8 +93,20 @@ class APO:
                "apo_create")
         self._h = h
 
+    @classmethod
+    def _view(cls, handle, dim, pop, max_iter, precision, owner):
+        """A batch member: same calls, no ownership (the batch frees it)."""
+        v = cls.__new__(cls)
+        v.dim, v.pop, v.max_iter, v.precision = int(dim), int(pop), int(max_iter), precision
+        v._h = handle
+        v._owner = owner
+        return v
+
     # -- life cycle -----------------------------------------------------
     def close(self):
+        if getattr(self, "_owner", None) is not None:   # a batch member
+            self._h = None
+            return
         if getattr(self, "_h", None):
             lib().apo_destroy(self._h)
             self._h = None
@@ -161,6 +176,98 @@ class APO:
                                    op.ctypes.data_as(C.POINTER(C.c_int32)),
                                    perm.ctypes.data_as(C.POINTER(C.c_int32))), "apo_get_trace")
         return Y, Fy, op, perm
+
+
+class Batch:
+    """Independent runs advanced together (``apo_batch_*``).
+
+    ``runs`` is a list of dicts with the keyword arguments of ``APO``
+    (dim, lb, ub, pop, np_pairs, pf_max, seed, max_iter, precision, kind,
+    shift, rot, hist, run_id, trace).  ``batch[i]`` is run i as an ``APO``
+    view (best, info, get_state, set_state, get_trace); ``run(n)`` steps
+    every run; ``tune(n)`` picks the launch schedule.
+    """
+
+    def __init__(self, runs, stream=None):
+        torch = _torch()
+        self._keep = []
+        self._specs = []
+        n = len(runs)
+        descs = (RunDesc * n)()
+        for i, r in enumerate(runs):
+            dim = int(r["dim"])
+            lb = np.ascontiguousarray(np.broadcast_to(np.asarray(r["lb"], np.float64), (dim,)))
+            ub = np.ascontiguousarray(np.broadcast_to(np.asarray(r["ub"], np.float64), (dim,)))
+            shift = r.get("shift")
+            shift = None if shift is None else np.ascontiguousarray(shift, np.float64).reshape(dim)
+            rot = r.get("rot")
+            rot = None if rot is None else np.ascontiguousarray(rot, np.float64).reshape(dim, dim)
+            hist = r.get("hist")
+            hist = None if hist is None else np.ascontiguousarray(hist, np.uint64).reshape(256)
+            self._keep += [lb, ub, shift, rot, hist]
+            prec = r.get("precision", "fp64")
+            d = descs[i]
+            d.dim = dim
+            d.lb, d.ub = _dptr(lb), _dptr(ub)
+            d.pop = int(r["pop"])
+            d.np = int(r.get("np_pairs", 1))
+            d.pf_max = float(r.get("pf_max", 0.1))
+            d.seed = int(r.get("seed", 1)) & (2**64 - 1)
+            d.opt = _options(r.get("max_iter", 100), prec, r.get("kind", "sphere"), shift, rot,
+                             hist, r.get("run_id", 0), APO_FLAG_TRACE if r.get("trace") else 0)
+            self._specs.append((dim, d.pop, int(r.get("max_iter", 100)), prec))
+        nbytes = int(lib().apo_batch_workspace_bytes(n, descs))
+        if nbytes == 0:
+            raise APOError(-1, "apo_batch_workspace_bytes")
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=torch.cuda.current_device())
+        o = BatchOptions()
+        o.stream = C.c_void_p(self._stream.cuda_stream)
+        o.workspace = C.c_void_p(self._ws.data_ptr())
+        o.workspace_bytes = nbytes
+        b = C.c_void_p()
+        _check(lib().apo_batch_create(n, descs, C.byref(o), C.byref(b)), "apo_batch_create")
+        self._b = b
+        self._members = []
+        for i in range(n):
+            h = C.c_void_p()
+            _check(lib().apo_batch_member(b, i, C.byref(h)), "apo_batch_member")
+            self._members.append(APO._view(h, *self._specs[i], owner=self))
+
+    def __len__(self):
+        return len(self._members)
+
+    def __getitem__(self, i):
+        return self._members[i]
+
+    def run(self, iters: int) -> int:
+        return _check(lib().apo_batch_run(self._b, int(iters)), "apo_batch_run")
+
+    def tune(self, iters: int = 16):
+        sched = C.c_int32()
+        us = np.zeros(4)
+        _check(lib().apo_batch_tune(self._b, int(iters), C.byref(sched), _dptr(us)),
+               "apo_batch_tune")
+        return sched.value, us
+
+    def close(self):
+        if getattr(self, "_b", None):
+            for m in self._members:
+                m._h = None
+            lib().apo_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def histogram_u8(img, stream=None):

@@ -34,6 +34,17 @@ class Options(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
+class RunDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("lb", C.POINTER(C.c_double)), ("ub", C.POINTER(C.c_double)),
+                ("pop", C.c_int32), ("np", C.c_int32), ("pf_max", C.c_double),
+                ("seed", C.c_uint64), ("opt", Options)]
+
+
+class BatchOptions(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
+
+
 class APOError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -81,6 +92,18 @@ def lib():
     L.apo_time_kernels.argtypes = [vp, i32, P(d)]
     L.apo_histogram_u8.restype = C.c_int
     L.apo_histogram_u8.argtypes = [vp, u64, vp, vp]
+    L.apo_batch_workspace_bytes.restype = C.c_size_t
+    L.apo_batch_workspace_bytes.argtypes = [i32, P(RunDesc)]
+    L.apo_batch_create.restype = C.c_int
+    L.apo_batch_create.argtypes = [i32, P(RunDesc), P(BatchOptions), P(vp)]
+    L.apo_batch_run.restype = C.c_int
+    L.apo_batch_run.argtypes = [vp, i32]
+    L.apo_batch_member.restype = C.c_int
+    L.apo_batch_member.argtypes = [vp, i32, P(vp)]
+    L.apo_batch_tune.restype = C.c_int
+    L.apo_batch_tune.argtypes = [vp, i32, P(i32), P(d)]
+    L.apo_batch_destroy.restype = C.c_int
+    L.apo_batch_destroy.argtypes = [vp]
     L.apo_strerror.restype = C.c_char_p
     L.apo_strerror.argtypes = [C.c_int]
     _lib = L

@@ -38,10 +38,9 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     const size_t es = o.precision == APO_FP64 ? 8 : 4;
     L.Dp = (int)align_up((size_t)dim, 64 / es);
     L.Nt = (dim + 15) / 16;
-    // k-steps of 4, padded with zeros to 32 (dim <= 128) or a multiple of 8,
-    // so the matrix-core loop runs unguarded in blocks of 8
-    L.Ks = (dim + 3) / 4;
-    L.Ks = L.Ks <= 32 ? 32 : (L.Ks + 7) / 8 * 8;
+    // k-steps of 4, padded with zeros to a multiple of 8 so the matrix-core
+    // loop runs unguarded in blocks of 8
+    L.Ks = ((dim + 3) / 4 + 7) / 8 * 8;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -153,6 +152,7 @@ struct apo {
     bool graph_tried;
     hipEvent_t ev[3];
     bool have_events;
+    bool batch_view;      // a member of a batch: stepped only through the batch
 };
 
 #define APO_HIP(h, call)                       \
@@ -162,6 +162,255 @@ struct apo {
             return APO_E_DEVICE;               \
         }                                      \
     } while (0)
+
+
+static int destroy_impl(apo_t *h);
+
+// ---------------------------------------------------------------------------
+// Batches of runs.  Each member is an ordinary handle whose workspace is a
+// slice of the batch workspace and whose stream is the batch stream; the
+// batch adds a device table of the members' parameters, the (run, block)
+// tables of its launches and the graphs that replay them.
+// ---------------------------------------------------------------------------
+struct BatchLaunchRec {
+    bool rank;                // a sort launch (else a step launch)
+    bool fp64;
+    int32_t proto;            // a member whose kernel shape the launch uses
+    std::vector<int> members; // runs covered, in member order
+    size_t lds;
+    int nblocks;
+    size_t table_off;         // first entry of its (run, block) table
+};
+
+struct apo_batch {
+    std::vector<apo_t *> runs;
+    hipStream_t stream;
+    bool own_stream;
+    unsigned char *ws;
+    bool own_ws;
+    size_t runs_bytes;        // the members' workspaces (the state the tuner saves)
+    Params *d_params;         // [n] members' parameters (in the workspace)
+    int2 *d_blocks;           // (run, block) tables (in the workspace)
+    size_t n_entries;
+    std::vector<BatchLaunchRec> launches;
+    std::vector<hipStream_t> side;     // parallel graph branches of the step launches
+    hipEvent_t fork_ev;
+    std::vector<hipEvent_t> join_ev;
+    int schedule;             // bit 0: parallel step branches; bit 1: interleaved blocks
+    hipGraph_t graph[2];
+    hipGraphExec_t gexec[2];
+    bool graphs_ready;
+    bool poisoned;
+};
+
+namespace {
+
+// Workspace layout of a batch: the members' workspaces, then the parameter
+// table, then the block tables.
+struct BatchLayout {
+    std::vector<size_t> run_off, run_bytes;
+    size_t runs_bytes, params_off, blocks_off, n_entries, total;
+};
+
+Params shape_params(const apo_run_desc &d) {
+    Params p;
+    std::memset(&p, 0, sizeof(p));
+    p.dim = d.dim;
+    p.pop = d.pop;
+    p.np = d.np;
+    p.kind = d.opt.objective.kind;
+    p.rotated = d.opt.objective.rot != nullptr;
+    return p;
+}
+
+int batch_layout(int32_t n, const apo_run_desc *runs, BatchLayout &B) {
+    if (n < 1 || !runs) return APO_E_INVAL;
+    B.run_off.resize(n);
+    B.run_bytes.resize(n);
+    size_t off = 0, entries = 0;
+    for (int i = 0; i < n; ++i) {
+        const apo_run_desc &d = runs[i];
+        if (d.opt.stream || d.opt.workspace || d.opt.workspace_bytes) return APO_E_INVAL;
+        const int chk = check_args(d.dim, d.lb, d.ub, d.pop, d.np, d.pf_max, &d.opt);
+        if (chk != APO_OK) return chk;
+        const Layout L = make_layout(d.dim, d.pop, d.opt);
+        B.run_off[i] = off;
+        B.run_bytes[i] = L.total;
+        off = align_up(off + L.total, 256);
+        const Params sp = shape_params(d);
+        entries += (size_t)apok::rank_blocks(sp) + (size_t)apok::step_blocks(sp);
+    }
+    B.runs_bytes = off;
+    B.params_off = off;
+    off = align_up(off + (size_t)n * sizeof(Params), 256);
+    B.blocks_off = off;
+    B.n_entries = entries;
+    B.total = align_up(off + entries * sizeof(int2), 256);
+    return APO_OK;
+}
+
+// The launches of one iteration: a sort per precision, then a step per
+// kernel shape, each over its members in member order.
+void batch_group_launches(apo_batch *b) {
+    b->launches.clear();
+    const int n = (int)b->runs.size();
+    for (int prec = 0; prec < 2; ++prec) {
+        BatchLaunchRec r{};
+        r.rank = true;
+        r.fp64 = prec == 1;
+        for (int i = 0; i < n; ++i)
+            if (b->runs[i]->fp64 == r.fp64) r.members.push_back(i);
+        if (r.members.empty()) continue;
+        r.proto = r.members[0];
+        b->launches.push_back(r);
+    }
+    std::vector<int> shapes;
+    for (int i = 0; i < n; ++i) {
+        const int sh = apok::step_shape(b->runs[i]->p, b->runs[i]->fp64);
+        bool seen = false;
+        for (int x : shapes) seen = seen || x == sh;
+        if (!seen) shapes.push_back(sh);
+    }
+    for (int sh : shapes) {
+        BatchLaunchRec r{};
+        r.rank = false;
+        for (int i = 0; i < n; ++i)
+            if (apok::step_shape(b->runs[i]->p, b->runs[i]->fp64) == sh) r.members.push_back(i);
+        r.proto = r.members[0];
+        r.fp64 = b->runs[r.proto]->fp64;
+        for (int i : r.members) {
+            const size_t l = apok::step_lds_bytes(b->runs[i]->p, b->runs[i]->fp64);
+            if (l > r.lds) r.lds = l;
+        }
+        b->launches.push_back(r);
+    }
+}
+
+// (run, block) tables of every launch for a schedule: run order (each run's
+// blocks together) or interleaved (block 0 of every run, then block 1, ...).
+int batch_fill_tables(apo_batch *b, int schedule) {
+    std::vector<int2> host;
+    host.reserve(b->n_entries);
+    for (BatchLaunchRec &r : b->launches) {
+        r.table_off = host.size();
+        std::vector<int> nb;
+        int most = 0;
+        for (int i : r.members) {
+            const Params &p = b->runs[i]->p;
+            nb.push_back(r.rank ? apok::rank_blocks(p) : apok::step_blocks(p));
+            if (nb.back() > most) most = nb.back();
+        }
+        if (schedule & 2) {
+            for (int k = 0; k < most; ++k)
+                for (size_t m = 0; m < r.members.size(); ++m)
+                    if (k < nb[m]) host.push_back(make_int2(r.members[m], k));
+        } else {
+            for (size_t m = 0; m < r.members.size(); ++m)
+                for (int k = 0; k < nb[m]; ++k) host.push_back(make_int2(r.members[m], k));
+        }
+        r.nblocks = (int)(host.size() - r.table_off);
+    }
+    if (host.size() > b->n_entries) return APO_E_STATE;
+    if (hipMemcpyAsync(b->d_blocks, host.data(), host.size() * sizeof(int2),
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        b->poisoned = true;
+        return APO_E_DEVICE;
+    }
+    return APO_OK;
+}
+
+// Enqueues `iters` iterations under the current schedule (on the batch
+// stream, or captured from it).
+hipError_t batch_enqueue(apo_batch *b, int32_t iters) {
+    const bool fork = (b->schedule & 1) != 0;
+    for (int32_t it = 0; it < iters; ++it) {
+        size_t k = 0;
+        for (const BatchLaunchRec &r : b->launches) {
+            apok::BatchLaunch bl;
+            bl.runs = b->d_params;
+            bl.blocks = b->d_blocks + r.table_off;
+            bl.nblocks = r.nblocks;
+            bl.lds = r.lds;
+            hipError_t e;
+            if (r.rank) {
+                e = apok::launch_rank_batch(bl, r.fp64, b->stream);
+                if (e != hipSuccess) return e;
+                continue;
+            }
+            if (!fork) {
+                e = apok::launch_step_batch(b->runs[r.proto]->p, r.fp64, bl, b->stream);
+                if (e != hipSuccess) return e;
+                continue;
+            }
+            if (k == 0) {
+                e = hipEventRecord(b->fork_ev, b->stream);
+                if (e != hipSuccess) return e;
+            }
+            e = hipStreamWaitEvent(b->side[k], b->fork_ev, 0);
+            if (e == hipSuccess)
+                e = apok::launch_step_batch(b->runs[r.proto]->p, r.fp64, bl, b->side[k]);
+            if (e == hipSuccess) e = hipEventRecord(b->join_ev[k], b->side[k]);
+            if (e != hipSuccess) return e;
+            ++k;
+        }
+        for (size_t j = 0; j < k; ++j) {
+            const hipError_t e = hipStreamWaitEvent(b->stream, b->join_ev[j], 0);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t batch_capture(apo_batch *b, int32_t iters, hipGraph_t *g, hipGraphExec_t *ge) {
+    *g = nullptr;
+    *ge = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t el = batch_enqueue(b, iters);
+    e = hipStreamEndCapture(b->stream, g);
+    if (el != hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(ge, *g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (*g) (void)hipGraphDestroy(*g);
+        *g = nullptr;
+        *ge = nullptr;
+    }
+    return e;
+}
+
+void batch_drop_graphs(apo_batch *b) {
+    for (int i = 0; i < 2; ++i) {
+        if (b->gexec[i]) (void)hipGraphExecDestroy(b->gexec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+        b->gexec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
+    b->graphs_ready = false;
+}
+
+int32_t batch_remaining(const apo_batch *b) {
+    int32_t rem = 0x7FFFFFFF;
+    for (const apo_t *h : b->runs)
+        if (h->T - h->t < rem) rem = h->T - h->t;
+    return rem;
+}
+
+int batch_destroy_impl(apo_batch *b) {
+    if (!b) return APO_OK;
+    if (b->stream && !b->poisoned) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    for (apo_t *h : b->runs) destroy_impl(h);
+    for (hipStream_t s : b->side) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->join_ev) (void)hipEventDestroy(e);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->own_ws && b->ws) (void)hipFree(b->ws);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return APO_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -198,7 +447,10 @@ static int destroy_impl(apo_t *h) {
     return APO_OK;
 }
 
-int apo_destroy(apo_t *h) { return destroy_impl(h); }
+int apo_destroy(apo_t *h) {
+    if (h && h->batch_view) return APO_E_STATE;
+    return destroy_impl(h);
+}
 
 int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int32_t np,
                double pf_max, uint64_t seed, const apo_options *opt, apo_t **out) {
@@ -250,6 +502,12 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     p.rotated = opt->objective.rot != nullptr;
     p.Nt = L.Nt;
     p.Ks = L.Ks;
+    {
+        // wide tiles only when the run alone still gives every CU a workgroup
+        const int wide = apok::tile_rows_wide(apok::lanes_for_dim(dim));
+        p.rows = (wide > 16 && pop >= 256 * wide) ? wide : 16;
+    }
+    p.rank_lds = pop <= 256 ? 1 : 0;   // one workgroup ranks the whole run
     p.trace = (opt->flags & APO_FLAG_TRACE) ? 1 : 0;
     p.seed_lo = (uint32_t)(seed & 0xFFFFFFFFu);
     p.seed_hi = (uint32_t)(seed >> 32);
@@ -362,6 +620,7 @@ static int launch_iteration(apo_t *h) {
 
 int apo_step(apo_t *h) {
     if (!h) return APO_E_INVAL;
+    if (h->batch_view) return APO_E_STATE;
     if (h->poisoned) return APO_E_DEVICE;
     if (h->t >= h->T) return APO_E_DONE;
     const int rc = launch_iteration(h);
@@ -408,6 +667,7 @@ static void capture_iterations(apo_t *h, int32_t iters, hipGraph_t *graph,
 
 int apo_run(apo_t *h, int32_t iters) {
     if (!h || iters < 0) return APO_E_INVAL;
+    if (h->batch_view) return APO_E_STATE;
     if (h->poisoned) return APO_E_DEVICE;
     int32_t n = h->T - h->t;
     if (iters < n) n = iters;
@@ -440,6 +700,7 @@ int apo_run(apo_t *h, int32_t iters) {
 
 int apo_time_kernels(apo_t *h, int32_t iters, double *avg_us) {
     if (!h || iters < 1 || !avg_us) return APO_E_INVAL;
+    if (h->batch_view) return APO_E_STATE;
     if (h->poisoned) return APO_E_DEVICE;
     int32_t n = h->T - h->t;
     if (iters < n) n = iters;
@@ -566,5 +827,195 @@ int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint32_t *d_hist, void *s
         return APO_E_DEVICE;
     return APO_OK;
 }
+
+
+size_t apo_batch_workspace_bytes(int32_t n, const apo_run_desc *runs) {
+    BatchLayout B;
+    return batch_layout(n, runs, B) == APO_OK ? B.total : 0;
+}
+
+int apo_batch_create(int32_t n, const apo_run_desc *runs, const apo_batch_options *opt,
+                     apo_batch_t **out) {
+    if (!out) return APO_E_INVAL;
+    *out = nullptr;
+    BatchLayout B;
+    const int chk = batch_layout(n, runs, B);
+    if (chk != APO_OK) return chk;
+    if (opt && opt->workspace && opt->workspace_bytes < B.total) return APO_E_INVAL;
+    apo_batch *b = new (std::nothrow) apo_batch();
+    if (!b) return APO_E_NOMEM;
+    if (opt && opt->stream) {
+        b->stream = (hipStream_t)opt->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return APO_E_DEVICE;
+        }
+        b->own_stream = true;
+    }
+    if (opt && opt->workspace) {
+        b->ws = (unsigned char *)opt->workspace;
+    } else {
+        if (hipMalloc((void **)&b->ws, B.total) != hipSuccess) {
+            b->ws = nullptr;
+            batch_destroy_impl(b);
+            return APO_E_NOMEM;
+        }
+        b->own_ws = true;
+    }
+    b->runs_bytes = B.runs_bytes;
+    b->d_params = (Params *)(b->ws + B.params_off);
+    b->d_blocks = (int2 *)(b->ws + B.blocks_off);
+    b->n_entries = B.n_entries;
+    for (int i = 0; i < n; ++i) {
+        apo_options o = runs[i].opt;
+        o.stream = b->stream;
+        o.workspace = b->ws + B.run_off[i];
+        o.workspace_bytes = B.run_bytes[i];
+        apo_t *h = nullptr;
+        const int rc = apo_create(runs[i].dim, runs[i].lb, runs[i].ub, runs[i].pop, runs[i].np,
+                                  runs[i].pf_max, runs[i].seed, &o, &h);
+        if (rc != APO_OK) {
+            batch_destroy_impl(b);
+            return rc;
+        }
+        h->batch_view = true;
+        // a batch fills the GPU with runs: fewer, fuller workgroups per run
+        h->p.rows = apok::tile_rows_wide(apok::lanes_for_dim(h->dim));
+        h->p.rank_lds = h->pop <= apok::kRankLdsMax ? 1 : 0;
+        b->runs.push_back(h);
+    }
+    std::vector<Params> hp(n);
+    for (int i = 0; i < n; ++i) hp[i] = b->runs[i]->p;
+    if (hipMemcpyAsync(b->d_params, hp.data(), (size_t)n * sizeof(Params), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess) {
+        b->poisoned = true;
+        batch_destroy_impl(b);
+        return APO_E_DEVICE;
+    }
+    batch_group_launches(b);
+    size_t steps = 0;
+    for (const BatchLaunchRec &r : b->launches) steps += r.rank ? 0 : 1;
+    b->side.assign(steps, nullptr);
+    b->join_ev.assign(steps, nullptr);
+    bool ok = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (size_t k = 0; ok && k < steps; ++k) {
+        ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join_ev[k], hipEventDisableTiming) == hipSuccess;
+    }
+    b->schedule = 0;
+    if (!ok || batch_fill_tables(b, b->schedule) != APO_OK) {
+        b->poisoned = true;
+        batch_destroy_impl(b);
+        return APO_E_DEVICE;
+    }
+    *out = b;
+    return APO_OK;
+}
+
+int apo_batch_member(apo_batch_t *b, int32_t i, apo_t **run) {
+    if (!b || !run || i < 0 || i >= (int32_t)b->runs.size()) return APO_E_INVAL;
+    *run = b->runs[i];
+    return APO_OK;
+}
+
+int apo_batch_run(apo_batch_t *b, int32_t iters) {
+    if (!b || iters < 0) return APO_E_INVAL;
+    if (b->poisoned) return APO_E_DEVICE;
+    for (const apo_t *h : b->runs) {
+        if (h->poisoned) return APO_E_DEVICE;
+        if (h->t != b->runs[0]->t) return APO_E_STATE;
+    }
+    int32_t n = batch_remaining(b);
+    if (iters < n) n = iters;
+    if (n <= 0) return 0;
+    if (!b->graphs_ready) {
+        b->graphs_ready = true;
+        if (batch_capture(b, 1, &b->graph[0], &b->gexec[0]) == hipSuccess &&
+            batch_remaining(b) >= kGraphBlock)
+            (void)batch_capture(b, kGraphBlock, &b->graph[1], &b->gexec[1]);
+        (void)hipGetLastError();
+    }
+    int32_t done = 0;
+    while (done < n) {
+        int32_t step;
+        hipError_t e;
+        if (b->gexec[1] && n - done >= kGraphBlock) {
+            e = hipGraphLaunch(b->gexec[1], b->stream);
+            step = kGraphBlock;
+        } else if (b->gexec[0]) {
+            e = hipGraphLaunch(b->gexec[0], b->stream);
+            step = 1;
+        } else {
+            e = batch_enqueue(b, 1);
+            step = 1;
+        }
+        if (e != hipSuccess) {
+            b->poisoned = true;
+            return APO_E_DEVICE;
+        }
+        done += step;
+        for (apo_t *h : b->runs) h->t += step;
+    }
+    return n;
+}
+
+int apo_batch_tune(apo_batch_t *b, int32_t iters, int32_t *schedule, double *us) {
+    if (!b || iters < 1) return APO_E_INVAL;
+    if (b->poisoned) return APO_E_DEVICE;
+    for (const apo_t *h : b->runs)
+        if (h->t != b->runs[0]->t) return APO_E_STATE;
+    int32_t n = batch_remaining(b);
+    if (iters < n) n = iters;
+    if (n < 1) return APO_E_DONE;
+    unsigned char *backup = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc((void **)&backup, b->runs_bytes) != hipSuccess) return APO_E_NOMEM;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+              hipMemcpyAsync(backup, b->ws, b->runs_bytes, hipMemcpyDeviceToDevice,
+                             b->stream) == hipSuccess;
+    double best = 1e300, t_us[4] = {0, 0, 0, 0};
+    int best_s = b->schedule;
+    batch_drop_graphs(b);
+    for (int sc = 0; ok && sc < 4; ++sc) {
+        b->schedule = sc;
+        ok = batch_fill_tables(b, sc) == APO_OK;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        ok = ok && batch_capture(b, n, &g, &ge) == hipSuccess;
+        float ms = 0.f;
+        for (int rep = 0; ok && rep < 2; ++rep) {   // warm-up, then timed
+            ok = hipEventRecord(e0, b->stream) == hipSuccess &&
+                 hipGraphLaunch(ge, b->stream) == hipSuccess &&
+                 hipEventRecord(e1, b->stream) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+                 hipMemcpyAsync(b->ws, backup, b->runs_bytes, hipMemcpyDeviceToDevice,
+                                b->stream) == hipSuccess;
+        }
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        t_us[sc] = 1000.0 * ms / n;
+        if (ok && t_us[sc] < best) {
+            best = t_us[sc];
+            best_s = sc;
+        }
+    }
+    ok = ok && hipStreamSynchronize(b->stream) == hipSuccess;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(backup);
+    b->schedule = best_s;
+    if (!ok || batch_fill_tables(b, best_s) != APO_OK) {
+        b->poisoned = true;
+        return APO_E_DEVICE;
+    }
+    if (schedule) *schedule = best_s;
+    if (us)
+        for (int i = 0; i < 4; ++i) us[i] = t_us[i];
+    return APO_OK;
+}
+
+int apo_batch_destroy(apo_batch_t *b) { return batch_destroy_impl(b); }
 
 }  // extern "C"

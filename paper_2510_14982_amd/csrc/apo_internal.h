@@ -12,7 +12,6 @@ enum : int32_t { K_SPHERE = 0, K_RASTRIGIN = 1, K_ROSENBROCK = 2, K_ACKLEY = 3, 
                  K_OTSU = 5 };
 
 constexpr int kMaxNp = 8;        // neighbour pairs supported
-constexpr int kTileRanks = 16;   // ranks per workgroup in the tiled step (one MFMA row block)
 
 // Device-resident control block, one per handle.  The rank kernel opens
 // iteration t_next = t + 1 and draws its scalars; the step kernel closes it.
@@ -34,6 +33,8 @@ struct Params {
     int32_t kind;         // objective
     int32_t rotated;      // 1: z = M (x - o) through the packed matrix
     int32_t Nt, Ks;       // MFMA tiles: output column tiles of 16, k-steps of 4
+    int32_t rows;         // ranks per workgroup of the tiled step: 16, or 512 / lanes
+    int32_t rank_lds;     // 1: the sort stages the keys in LDS (pop <= 1024)
                           // (Ks padded to 32 or a multiple of 8; A and B zero there)
     int32_t trace;        // 1: write candidates to the trace buffers
     uint32_t seed_lo, seed_hi, run;
@@ -56,6 +57,16 @@ struct Params {
     int32_t *trOp;        // [pop]
 };
 
+// A batched launch: workgroup b runs block blocks[b].y of run blocks[b].x,
+// whose parameters are runs[blocks[b].x] (device arrays); lds is the
+// dynamic LDS of the launch (the largest of its runs).
+struct BatchLaunch {
+    const Params *runs;
+    const int2 *blocks;
+    int nblocks;
+    size_t lds;
+};
+
 // Launchers (apo_kernels.hip).  All asynchronous on `s`; they return the
 // launch status.
 hipError_t launch_init(const Params &p, bool fp64, hipStream_t s);
@@ -65,8 +76,21 @@ hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hip
 hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream_t s);
 hipError_t launch_histogram(const uint8_t *img, uint64_t n, uint32_t *hist, hipStream_t s);
 
+// Batches: every run of a step launch has the same kernel shape
+// (step_shape), one rank launch per precision.
+hipError_t launch_rank_batch(const BatchLaunch &b, bool fp64, hipStream_t s);
+hipError_t launch_step_batch(const Params &proto, bool fp64, const BatchLaunch &b, hipStream_t s);
+int rank_blocks(const Params &p);              // workgroups of a run's sort
+int step_blocks(const Params &p);              // workgroups of a run's step
+size_t step_lds_bytes(const Params &p, bool fp64);
+int step_shape(const Params &p, bool fp64);    // equal iff one kernel serves both runs
+
 // Lanes per protozoan and 4-element chunks per lane used for a dimension.
 int lanes_for_dim(int dim);
+// Largest population the LDS form of the sort takes.
+constexpr int kRankLdsMax = 1024;
+// Rows per workgroup of the wide tiled step for G lanes per protozoan.
+constexpr int tile_rows_wide(int G) { return 512 / G > 16 ? 512 / G : 16; }
 int chunks_for_dim(int dim);
 
 

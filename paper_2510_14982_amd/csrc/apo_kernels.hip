@@ -74,7 +74,7 @@ __device__ __forceinline__ void open_iteration(const Params &p, int t, uint32_t 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void rank_kernel(Params p) {
+__device__ __forceinline__ void rank_body(const Params &p, int blk) {
     __shared__ uint64_t s_ki[kRankPer];
     __shared__ int32_t part[4][kRankPer];
     __shared__ uint32_t s_keys[24];
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
     const T *F = (const T *)p.F;
     const int ps = p.pop;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int i0 = blockIdx.x * kRankPer;
+    const int i0 = blk * kRankPer;
     // the iteration this sort opens (a vector load: the key loads below are
     // issued without waiting for it)
     const int t = __hip_atomic_load(&p.ctrl->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
@@ -120,6 +120,7 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
         }
 #pragma unroll
         for (int u = 0; u < kRankJ; ++u) {
+            if (base + 256 * u >= ps) break;   // the rest of the pass is padding
             const int j = base + 256 * u + tid;
 #pragma unroll
             for (int q = 0; q < kRankPer; ++q)
@@ -146,13 +147,86 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
         for (int q = 0; q < 24; ++q) drs.k[q] = s_keys[q];
         p.drf[rank] = subset_has(drs, (uint32_t)rank, (uint32_t)s_mdr) ? 1 : 0;
     }
-    if (blockIdx.x == 0 && tid == 64) {   // publish the iteration for the step
+    if (blk == 0 && tid == 64) {   // publish the iteration for the step
         p.ctrl->m_dr = s_mdr;
         p.ctrl->p_ah = p.p_ah[t];
         p.ctrl->fscale = p.fscale[t];
         p.ctrl->cnear = p.cnear[t];
         p.ctrl->t_next = t;
     }
+}
+
+// LDS form (ps <= kRankLdsMax): the run's keys are staged in LDS and each
+// of the workgroup's 256 threads counts, for one protozoan, the keys that
+// precede its own (broadcast reads), so a workgroup ranks 256 protozoa.
+// Fewest workgroups: the form of small runs and of batches; a single run
+// of a few hundred or more protozoa prefers the register form's many
+// workgroups (lower latency).
+constexpr int kRankSmall = kRankLdsMax;
+
+template <typename T>
+__device__ __forceinline__ void rank_small_body(const Params &p, int blk) {
+    __shared__ uint64_t s_k[kRankSmall];
+    __shared__ uint32_t s_keys[24];
+    __shared__ int32_t s_mdr;
+    const T *F = (const T *)p.F;
+    const int ps = p.pop;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int t = __hip_atomic_load(&p.ctrl->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    T f[kRankSmall / 256];
+#pragma unroll
+    for (int u = 0; u < kRankSmall / 256; ++u) {
+        const int j = tid + 256 * u;
+        f[u] = F[j < ps ? j : ps - 1];
+    }
+    if (wave == 3) open_iteration(p, t, s_keys, &s_mdr);
+#pragma unroll
+    for (int u = 0; u < kRankSmall / 256; ++u) {
+        const int j = tid + 256 * u;
+        if (j < ps) s_k[j] = RankKey<T>::make(f[u], j);
+    }
+    __syncthreads();
+    const int i = blk * 256 + tid;
+    if (i < ps) {
+        const uint64_t ki = s_k[i];
+        int rank = 0;
+        for (int j = 0; j < ps; ++j) rank += RankKey<T>::before(s_k[j], j, ki, i) ? 1 : 0;
+        p.perm[rank] = i;
+        ((T *)p.Fs)[rank] = F[i];
+        Subset drs;
+        subset_shape(drs, (uint32_t)ps);
+#pragma unroll
+        for (int q = 0; q < 24; ++q) drs.k[q] = s_keys[q];
+        p.drf[rank] = subset_has(drs, (uint32_t)rank, (uint32_t)s_mdr) ? 1 : 0;
+    }
+    if (blk == 0 && tid == 64) {   // publish the iteration for the step
+        p.ctrl->m_dr = s_mdr;
+        p.ctrl->p_ah = p.p_ah[t];
+        p.ctrl->fscale = p.fscale[t];
+        p.ctrl->cnear = p.cnear[t];
+        p.ctrl->t_next = t;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void rank_any(const Params &p, int blk) {
+    if (p.rank_lds)
+        rank_small_body<T>(p, blk);
+    else
+        rank_body<T>(p, blk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void rank_kernel(Params p) {
+    rank_any<T>(p, (int)blockIdx.x);
+}
+
+// Several runs in one launch: workgroup b sorts block blocks[b].y of run
+// blocks[b].x.
+template <typename T>
+__global__ __launch_bounds__(256) void rank_kernel_batch(const Params *runs, const int2 *blocks) {
+    const int2 b = blocks[blockIdx.x];
+    rank_any<T>(runs[b.x], b.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,6 +356,10 @@ hipError_t launch_elem_f32(const Params &p, int init, hipStream_t s);
 hipError_t launch_elem_f64(const Params &p, int init, hipStream_t s);
 hipError_t launch_tile_f32(const Params &p, int init, hipStream_t s);
 hipError_t launch_tile_f64(const Params &p, int init, hipStream_t s);
+hipError_t launch_elem_batch_f32(const Params &proto, const BatchLaunch &b, hipStream_t s);
+hipError_t launch_elem_batch_f64(const Params &proto, const BatchLaunch &b, hipStream_t s);
+hipError_t launch_tile_batch_f32(const Params &proto, const BatchLaunch &b, hipStream_t s);
+hipError_t launch_tile_batch_f64(const Params &proto, const BatchLaunch &b, hipStream_t s);
 
 static hipError_t launch_step_any(const Params &p, bool fp64, int init, hipStream_t s) {
     const bool tile = p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
@@ -298,12 +376,51 @@ hipError_t launch_step(const Params &p, bool fp64, hipStream_t s) {
 }
 
 hipError_t launch_rank(const Params &p, bool fp64, hipStream_t s) {
-    const dim3 grid((p.pop + kRankPer - 1) / kRankPer), block(256);
+    const dim3 grid((unsigned)rank_blocks(p)), block(256);
     if (fp64)
         hipLaunchKernelGGL(rank_kernel<double>, grid, block, 0, s, p);
     else
         hipLaunchKernelGGL(rank_kernel<float>, grid, block, 0, s, p);
     return hipGetLastError();
+}
+
+hipError_t launch_rank_batch(const BatchLaunch &b, bool fp64, hipStream_t s) {
+    const dim3 grid((unsigned)b.nblocks), block(256);
+    if (fp64)
+        hipLaunchKernelGGL(rank_kernel_batch<double>, grid, block, 0, s, b.runs, b.blocks);
+    else
+        hipLaunchKernelGGL(rank_kernel_batch<float>, grid, block, 0, s, b.runs, b.blocks);
+    return hipGetLastError();
+}
+
+static bool tile_form(const Params &p) {
+    return p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
+}
+
+hipError_t launch_step_batch(const Params &proto, bool fp64, const BatchLaunch &b, hipStream_t s) {
+    if (tile_form(proto))
+        return fp64 ? launch_tile_batch_f64(proto, b, s) : launch_tile_batch_f32(proto, b, s);
+    return fp64 ? launch_elem_batch_f64(proto, b, s) : launch_elem_batch_f32(proto, b, s);
+}
+
+int rank_blocks(const Params &p) {
+    return p.rank_lds ? (p.pop + 255) / 256 : (p.pop + kRankPer - 1) / kRankPer;
+}
+
+int step_blocks(const Params &p) {
+    if (tile_form(p)) return (p.pop + tile_rows(p) - 1) / tile_rows(p);
+    return (int)(((long long)p.pop * lanes_for_dim(p.dim) + 255) / 256);
+}
+
+size_t step_lds_bytes(const Params &p, bool fp64) {
+    return tile_form(p) ? tile_lds_bytes(p, fp64) : 0;
+}
+
+// Instantiation key: precision, form, lanes, chunks and whether np > 1.
+int step_shape(const Params &p, bool fp64) {
+    return (fp64 ? 1 : 0) | (tile_form(p) ? 2 : 0) | (p.np > 1 ? 4 : 0) |
+           (lanes_for_dim(p.dim) << 3) | (chunks_for_dim(p.dim) << 12) |
+           ((tile_form(p) ? tile_rows(p) : 0) << 16);
 }
 
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s) {

@@ -399,9 +399,9 @@ __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX>
 // group never straddles a wavefront), NCH chunks of 4 coordinates per lane.
 // ---------------------------------------------------------------------------
 template <typename T, int G, int NCH, int NPMAX>
-__global__ __launch_bounds__(256) void step_elem(Params p, int init) {
+__device__ __forceinline__ void step_elem_body(const Params &p, int init, int blk) {
     const int lane = threadIdx.x & (G - 1);
-    const int item = (blockIdx.x * 256 + threadIdx.x) / G;
+    const int item = (blk * 256 + threadIdx.x) / G;
     if (item >= p.pop) return;
     const int D = p.dim, Dp = p.Dp;
     const Iter it = load_iter(p, init);
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
         if (d0 < D) store4(row + d0, accept ? ys[ch] : xs[ch]);
     }
     if (lane == 0) Fn[c.id] = accept ? fnew : c.fold;
-    if (!init && blockIdx.x == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
+    if (!init && blk == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
     if (p.trace && !init) {
         T *ty = (T *)p.trY + (size_t)c.id * Dp;
 #pragma unroll
@@ -522,10 +522,26 @@ __global__ __launch_bounds__(256) void step_elem(Params p, int init) {
     }
 }
 
+// One handle's launch: workgroup b is the run's block b.  A batch launch
+// covers several runs with the same kernel shape: workgroup b does block
+// blocks[b].y of run blocks[b].x, whose parameters are runs[blocks[b].x].
+template <typename T, int G, int NCH, int NPMAX>
+__global__ __launch_bounds__(256) void step_elem(Params p, int init) {
+    step_elem_body<T, G, NCH, NPMAX>(p, init, (int)blockIdx.x);
+}
+template <typename T, int G, int NCH, int NPMAX>
+__global__ __launch_bounds__(256) void step_elem_batch(const Params *runs, const int2 *blocks,
+                                                       int init) {
+    const int2 b = blocks[blockIdx.x];
+    step_elem_body<T, G, NCH, NPMAX>(runs[b.x], init, b.y);
+}
+
 // ---------------------------------------------------------------------------
-// Tiled step: 16 protozoa per workgroup of 512 threads.
-// LDS: Ys[16][LS] candidates, Xs[16][LS] own rows, Zs[16][LZ] transformed
-// coordinates (rotated objectives) or sorted thresholds (histogram ones).
+// Tiled step: TM = max(16, 512 / G) consecutive ranks per workgroup of 512
+// threads (one lane group per row; TM / 16 MFMA row blocks).
+// LDS: Ys, Xs, As [TM][LS] candidates, own rows and y - o; Zs [TM][LZ]
+// transformed coordinates (Rosenbrock) or sorted thresholds (histogram
+// objectives); per-(row, column tile) partial sums [TM][Nt] x 2.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -594,19 +610,26 @@ __device__ __forceinline__ double threshold_objective_team(const Params &p, cons
 
 // LDS row stride (elements) of the tile's row buffers.  The matrix-core A
 // operand is read as 16-byte vectors by 16 lanes of 16 different rows at a
-// time; a stride of 4 words (mod 64) puts those rows in 16 distinct groups
-// of four banks.  The stride is a multiple of 16 bytes, so rows are also
-// written as 16-byte vectors.
+// time; a stride of an odd number of 16-byte units puts those rows in 16
+// distinct groups of four banks.  Rows are also written as 16-byte vectors.
 __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
     const int w = p.Dp > 4 * p.Ks ? p.Dp : 4 * p.Ks;
-    const int mod = 256 / es, off = 16 / es;      // 64 words and 4 words, in elements
-    return (w - off + mod - 1) / mod * mod + off;
+    const int per = 16 / es;                      // elements per 16 bytes
+    int q = (w + per - 1) / per;
+    if ((q & 1) == 0) ++q;
+    return q * per;
 }
 
-template <typename T, int G, int NCH, int NPMAX>
-__global__ __launch_bounds__(512) void step_tile(Params p, int init) {
-    constexpr int NT = 512, TM = kTileRanks, GROUPS = NT / G;
-    static_assert(NT / 32 == TM, "one 32-lane team per row in the thresholding phase");
+// Rows (consecutive ranks) per workgroup of the tiled step: one MFMA row
+// block of 16, or "wide" -- one row per lane group of the 512 threads --
+// which fills every thread when the lane groups are small (fewer, fuller
+// workgroups: the choice of batches and of very large populations).
+inline int tile_rows(const Params &p) { return p.rows > 16 ? p.rows : 16; }
+
+template <typename T, int G, int NCH, int NPMAX, int TM>
+__device__ __forceinline__ void step_tile_body(const Params &p, int init, int blk) {
+    constexpr int NT = 512, GROUPS = NT / G, RB = TM / 16;
+    static_assert(TM % 16 == 0 && TM % (NT / 32) == 0, "row blocks of 16; teams of 32 lanes");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_id[TM], s_op[TM];
     __shared__ uint32_t s_mwords[GROUPS][(4 * G * NCH + 31) / 32];
@@ -617,7 +640,9 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     T *Xs = Ys + TM * LS;     // own rows
     T *As = Xs + TM * LS;     // y - o, the matrix-core A operand
     T *Zs = As + TM * LS;     // z = M (y - o) when a coordinate's neighbour is needed
-    __shared__ T s_p1[TM][32], s_p2[TM][32];   // per column-tile partial sums
+    const int zwords = TM * LZ > TM * (D + 1) ? TM * LZ : TM * (D + 1);
+    T *s_p1 = Zs + zwords;    // [TM][Nt] per column-tile partial sums
+    T *s_p2 = s_p1 + TM * p.Nt;
     const Iter it = load_iter(p, init);
     const int t = it.t;
     const int src = (t + 1) & 1, dst = t & 1;
@@ -626,20 +651,21 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     T *Xn = (T *)p.X[dst];
     T *Fn = (T *)p.F;
     const T *o = (const T *)p.shift;
-    const int r0 = blockIdx.x * TM;
+    const int r0 = blk * TM;
     const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
 
-    // The first column tile of each wavefront's B fragments (packed M^T) is
-    // requested before phase 1 so the loads overlap the candidate work.
+    // The B fragments (packed M^T) of each wavefront's first output tile
+    // are requested before phase 1 so the loads overlap the candidate work,
+    // when the K range is exactly PRE steps (one straight MFMA run).
     constexpr int PRE = sizeof(T) == 4 ? 32 : 16;
     T bpre[PRE];
     {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
         const T *B = (const T *)p.rotp;
-        if (p.rotated && wave < p.Nt) {
-            // the packed K range holds at least 32 steps (zero padded)
+        if (p.rotated && p.Ks == PRE && wave < RB * p.Nt) {
+            const int nt0 = wave % p.Nt;
 #pragma unroll
-            for (int ks = 0; ks < PRE; ++ks) bpre[ks] = B[((size_t)ks * p.Nt + wave) * 64 + l];
+            for (int ks = 0; ks < PRE; ++ks) bpre[ks] = B[((size_t)ks * p.Nt + nt0) * 64 + l];
         } else {
 #pragma unroll
             for (int ks = 0; ks < PRE; ++ks) bpre[ks] = T(0);
@@ -720,13 +746,15 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
         const typename V4<T>::type zero = {T(0), T(0), T(0), T(0)};
         const T *B = (const T *)p.rotp;
         const int i = l & 15;
+        // output tile tau = (row block rb, column tile nt), wavefronts in turn;
         // the contraction index of step ks in lane l is k = Ks (l / 16) + ks
         // (the host packs B with the same order), so a lane's A values are
-        // contiguous: A[i][Ks (l / 16) + ks] at Arow[ks]
-        const T *Arow = As + i * LS + (l >> 4) * p.Ks;
-        for (int nt = wave; nt < p.Nt; nt += NT / 64) {
+        // contiguous: A[16 rb + i][Ks (l / 16) + ks] at Arow[ks]
+        for (int tau = wave; tau < RB * p.Nt; tau += NT / 64) {
+            const int rb = tau / p.Nt, nt = tau % p.Nt;
+            const T *Arow = As + (16 * rb + i) * LS + (l >> 4) * p.Ks;
             typename V4<T>::type acc = zero;
-            if (nt == wave && p.Ks == PRE) {
+            if (tau == wave && p.Ks == PRE) {
                 // fragments already in registers: one straight run
                 T a[PRE];
 #pragma unroll
@@ -747,7 +775,7 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
             if (p.kind == K_ROSENBROCK) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    Zs[mfma_out_row<T>(l, v) * LZ + 16 * nt + (l & 15)] = acc[v];
+                    Zs[(16 * rb + mfma_out_row<T>(l, v)) * LZ + 16 * nt + (l & 15)] = acc[v];
             } else {
                 // separable objectives straight from the accumulators: the
                 // 16 columns of this tile summed per row (butterfly over the
@@ -768,8 +796,9 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
                     g1 = group_sum<16>(g1);
                     if (p.kind == K_ACKLEY) g2 = group_sum<16>(g2);
                     if ((l & 15) == 0) {
-                        s_p1[mfma_out_row<T>(l, v)][nt] = g1;
-                        s_p2[mfma_out_row<T>(l, v)][nt] = g2;
+                        const int row = 16 * rb + mfma_out_row<T>(l, v);
+                        s_p1[row * p.Nt + nt] = g1;
+                        s_p2[row * p.Nt + nt] = g2;
                     }
                 }
             }
@@ -779,12 +808,14 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
 
     // phase 3: objective per protozoan
     if (thresholds) {
-        // one 32-lane team per row (the 512 threads are 16 teams)
-        const int row = threadIdx.x >> 5, tl = threadIdx.x & 31;
-        const bool live = s_id[row] >= 0;
-        int *ts = (int *)Zs + row * (D + 1);
-        const double f = threshold_objective_team<T>(p, Ys + row * LS, ts, tl, live);
-        if (tl == 0 && live) s_fnew[row] = T(f);
+        // 32-lane teams (the 512 threads are 16 teams), rows in turn
+        const int tl = threadIdx.x & 31;
+        for (int row = threadIdx.x >> 5; row < TM; row += NT / 32) {
+            const bool live = s_id[row] >= 0;
+            int *ts = (int *)Zs + row * (D + 1);
+            const double f = threshold_objective_team<T>(p, Ys + row * LS, ts, tl, live);
+            if (tl == 0 && live) s_fnew[row] = T(f);
+        }
     } else if (separable) {
         // the row sums of the column-tile partials are taken in phase 4 by
         // each row's own group (the partials are visible since phase 2)
@@ -821,7 +852,7 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     if (!separable) __syncthreads();
 
     // phase 4: greedy selection and the double-buffered write
-    if (!init && blockIdx.x == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
+    if (!init && blk == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
     for (int row = grp; row < TM; row += GROUPS) {
         const int id = s_id[row];
         if (id < 0) continue;
@@ -829,9 +860,9 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
         if (separable) {
             // the same sequential sum in every lane (broadcast LDS reads)
             T s1 = T(0), s2 = T(0);
-            for (int nt = 0; nt < p.Nt; ++nt) s1 += s_p1[row][nt];
+            for (int nt = 0; nt < p.Nt; ++nt) s1 += s_p1[row * p.Nt + nt];
             if (p.kind == K_ACKLEY)
-                for (int nt = 0; nt < p.Nt; ++nt) s2 += s_p2[row][nt];
+                for (int nt = 0; nt < p.Nt; ++nt) s2 += s_p2[row * p.Nt + nt];
             fnew = p.kind == K_ACKLEY
                        ? T(-20) * exp(T(-0.2) * sqrt(s1 / T(D))) - exp(s2 / T(D)) + T(20) + T(kE)
                        : s1;
@@ -862,54 +893,78 @@ __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     }
 }
 
+template <typename T, int G, int NCH, int NPMAX, int TM>
+__global__ __launch_bounds__(512) void step_tile(Params p, int init) {
+    step_tile_body<T, G, NCH, NPMAX, TM>(p, init, (int)blockIdx.x);
+}
+template <typename T, int G, int NCH, int NPMAX, int TM>
+__global__ __launch_bounds__(512) void step_tile_batch(const Params *runs, const int2 *blocks,
+                                                       int init) {
+    const int2 b = blocks[blockIdx.x];
+    step_tile_body<T, G, NCH, NPMAX, TM>(runs[b.x], init, b.y);
+}
 
 inline bool use_tile(const Params &p) {
     return p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
 }
 
 inline size_t tile_lds_bytes(const Params &p, bool fp64) {
-    const size_t es = fp64 ? 8 : 4;
+    const size_t es = fp64 ? 8 : 4, TM = (size_t)tile_rows(p);
     const size_t LS = (size_t)tile_row_stride(p, (int)es), LZ = (size_t)p.Nt * 16 + 1;
-    size_t z = kTileRanks * LZ * es;
-    const size_t ts = kTileRanks * ((size_t)p.dim + 1) * sizeof(int);
-    if (ts > z) z = ts;
-    return 3 * kTileRanks * LS * es + z;
+    const size_t zwords = TM * LZ > TM * ((size_t)p.dim + 1) ? TM * LZ : TM * ((size_t)p.dim + 1);
+    return (3 * TM * LS + zwords + 2 * TM * (size_t)p.Nt) * es;
 }
 
+// A launch of one handle (b == nullptr: grid of the run's own blocks, lds
+// from its shape) or of a batch (b: the runs of one kernel shape, `p` one
+// of them, lds the largest of theirs).
 template <typename T, int NPMAX>
-hipError_t launch_tile_t(const Params &p, int init, hipStream_t s) {
+hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLaunch *b = nullptr) {
     const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
     if (NCH < 0) return hipErrorInvalidValue;
     {
-        const dim3 grid((p.pop + kTileRanks - 1) / kTileRanks), block(512);
-        const size_t lds = tile_lds_bytes(p, sizeof(T) == 8);
-#define APO_TILE(GG, CC)                                                                     \
-    if (G == GG && NCH == CC) {                                                              \
+        const int TMr = tile_rows(p);
+        const dim3 grid(b ? (unsigned)b->nblocks : (unsigned)((p.pop + TMr - 1) / TMr));
+        const dim3 block(512);
+        const size_t lds = b ? b->lds : tile_lds_bytes(p, sizeof(T) == 8);
+#define APO_TILE(GG, CC, TMM)                                                                \
+    if (G == GG && NCH == CC && TMr == TMM) {                                                \
+        const void *fn = b ? (const void *)step_tile_batch<T, GG, CC, NPMAX, TMM>           \
+                           : (const void *)step_tile<T, GG, CC, NPMAX, TMM>;                 \
         if (lds > 65536) {                                                                   \
-            const hipError_t ea = hipFuncSetAttribute(                                       \
-                (const void *)step_tile<T, GG, CC, NPMAX>,                                   \
-                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                       \
+            const hipError_t ea =                                                            \
+                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
             if (ea != hipSuccess) return ea;                                                 \
         }                                                                                    \
-        hipLaunchKernelGGL((step_tile<T, GG, CC, NPMAX>), grid, block, lds, s, p, init);     \
+        if (b)                                                                               \
+            hipLaunchKernelGGL((step_tile_batch<T, GG, CC, NPMAX, TMM>), grid, block, lds, s, \
+                               b->runs, b->blocks, init);                                    \
+        else                                                                                 \
+            hipLaunchKernelGGL((step_tile<T, GG, CC, NPMAX, TMM>), grid, block, lds, s, p,   \
+                               init);                                                        \
         return hipGetLastError();                                                            \
     }
-        APO_TILE(4, 1) APO_TILE(8, 1) APO_TILE(16, 1) APO_TILE(32, 1) APO_TILE(64, 1)
-        APO_TILE(64, 2)
+        APO_TILE(4, 1, 16) APO_TILE(8, 1, 16) APO_TILE(16, 1, 16) APO_TILE(32, 1, 16)
+        APO_TILE(64, 1, 16) APO_TILE(64, 2, 16)
+        APO_TILE(4, 1, 128) APO_TILE(8, 1, 64) APO_TILE(16, 1, 32)
 #undef APO_TILE
         return hipErrorInvalidValue;
     }
 }
 
 template <typename T, int NPMAX>
-hipError_t launch_elem_t(const Params &p, int init, hipStream_t s) {
+hipError_t launch_elem_t(const Params &p, int init, hipStream_t s, const BatchLaunch *b = nullptr) {
     const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
     if (NCH < 0) return hipErrorInvalidValue;
     const long long threads = (long long)p.pop * G;
-    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+    const dim3 grid(b ? (unsigned)b->nblocks : (unsigned)((threads + 255) / 256)), block(256);
 #define APO_ELEM(GG, CC)                                                                     \
     if (G == GG && NCH == CC) {                                                              \
-        hipLaunchKernelGGL((step_elem<T, GG, CC, NPMAX>), grid, block, 0, s, p, init);       \
+        if (b)                                                                               \
+            hipLaunchKernelGGL((step_elem_batch<T, GG, CC, NPMAX>), grid, block, 0, s,       \
+                               b->runs, b->blocks, init);                                    \
+        else                                                                                 \
+            hipLaunchKernelGGL((step_elem<T, GG, CC, NPMAX>), grid, block, 0, s, p, init);   \
         return hipGetLastError();                                                            \
     }
     APO_ELEM(4, 1) APO_ELEM(8, 1) APO_ELEM(16, 1) APO_ELEM(32, 1) APO_ELEM(64, 1)

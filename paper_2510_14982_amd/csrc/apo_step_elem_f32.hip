@@ -7,4 +7,9 @@ hipError_t launch_elem_f32(const Params &p, int init, hipStream_t s) {
     return p.np == 1 ? launch_elem_t<float, 1>(p, init, s) : launch_elem_t<float, kMaxNp>(p, init, s);
 }
 
+hipError_t launch_elem_batch_f32(const Params &proto, const BatchLaunch &b, hipStream_t s) {
+    return proto.np == 1 ? launch_elem_t<float, 1>(proto, 0, s, &b)
+                         : launch_elem_t<float, kMaxNp>(proto, 0, s, &b);
+}
+
 }  // namespace apok

@@ -7,4 +7,9 @@ hipError_t launch_elem_f64(const Params &p, int init, hipStream_t s) {
     return p.np == 1 ? launch_elem_t<double, 1>(p, init, s) : launch_elem_t<double, kMaxNp>(p, init, s);
 }
 
+hipError_t launch_elem_batch_f64(const Params &proto, const BatchLaunch &b, hipStream_t s) {
+    return proto.np == 1 ? launch_elem_t<double, 1>(proto, 0, s, &b)
+                         : launch_elem_t<double, kMaxNp>(proto, 0, s, &b);
+}
+
 }  // namespace apok

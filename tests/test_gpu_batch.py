@@ -1,0 +1,95 @@
+"""Batched runs: every run of a batch computes exactly what a standalone
+handle with the same arguments computes (same kernels, draws and
+arithmetic), under every launch schedule the autotuner can pick, and the
+batch's member views behave as documented."""
+import numpy as np
+import pytest
+
+import gen
+from gpu_common import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _spec(w, precision=None):
+    return dict(dim=w.dim, lb=w.lb, ub=w.ub, pop=w.pop, np_pairs=w.np_pairs, pf_max=w.pf_max,
+                seed=w.seed, max_iter=w.max_iter, precision=precision or w.precision,
+                kind=w.kind, shift=w.shift, rot=w.rot, hist=w.hist, run_id=w.run)
+
+
+def _mixed_runs(max_iter=40):
+    """Rotated FP32 runs of four dimensions and three objectives, plus an
+    elementwise FP64 run, a Kapur run and a run with three neighbour pairs."""
+    runs = [_spec(w) for w in gen.batched_runs(n=9, seed=7, max_iter=max_iter,
+                                               dims=(10, 20, 50, 100), pops=(64, 130),
+                                               kinds=("rastrigin", "rosenbrock", "ackley"))]
+    w = gen.shifted_rastrigin_small(seed=3)
+    runs.append(dict(_spec(w), max_iter=max_iter))
+    img = gen.blob_image(128, 128, seed=2)
+    runs.append(dict(dim=4, lb=0.0, ub=255.0, pop=70, seed=5, max_iter=max_iter,
+                     precision="fp32", kind="kapur", hist=gen.histogram_of(img)))
+    runs.append(dict(dim=33, lb=-5.0, ub=5.0, pop=50, np_pairs=3, seed=9, max_iter=max_iter,
+                     precision="fp64", kind="ackley"))
+    return runs
+
+
+def _standalone(apo, spec, iters):
+    with apo.APO(**spec) as g:
+        g.run(iters)
+        return g.get_state()
+
+
+@pytest.mark.parametrize("schedule_trials", [False, True])
+def test_batch_equals_standalone_runs(schedule_trials):
+    apo = need_gpu()
+    print(f"[batch] mixed runs, tune={schedule_trials}", flush=True)
+    runs = _mixed_runs()
+    with apo.Batch(runs) as b:
+        if schedule_trials:
+            sched, us = b.tune(8)
+            print(f"[batch] schedule {sched} us/iter {us}", flush=True)
+        assert b.run(13) == 13
+        assert b.run(20) == 20
+        for i, spec in enumerate(runs):
+            X, F, t = b[i].get_state()
+            Xs, Fs, ts = _standalone(apo, spec, 33)
+            assert t == ts == 33
+            assert np.array_equal(X, Xs), i
+            assert np.array_equal(F, Fs), i
+        assert b.run(100) == 7          # budget of 40 iterations
+        assert b.run(5) == 0
+        xb, fb, fes = b[0].best()
+        assert fes == runs[0]["pop"] * 41
+
+
+def test_batch_members_are_views():
+    apo = need_gpu()
+    print("[batch] views", flush=True)
+    runs = _mixed_runs(max_iter=10)[:3]
+    with apo.Batch(runs) as b:
+        with pytest.raises(apo.APOError):
+            b[0].step()
+        with pytest.raises(apo.APOError):
+            b[1].run(1)
+        X, F, t = b[2].get_state()
+        b[2].set_state(X, F, 3)            # members no longer at one iteration
+        with pytest.raises(apo.APOError):
+            b.run(1)
+        b[2].set_state(X, F, 0)
+        assert b.run(2) == 2
+
+
+def test_batch_of_512_shape():
+    """The full batched configuration's shape (512 runs; dims 10..100, pops
+    64..1024, three rotated objectives) for a few iterations, each run
+    checked against its standalone handle on a sample."""
+    apo = need_gpu()
+    print("[batch] 512 runs x 5 iterations", flush=True)
+    ws = gen.batched_runs(n=512, seed=1, max_iter=1000)
+    runs = [_spec(w) for w in ws]
+    with apo.Batch(runs) as b:
+        assert b.run(5) == 5
+        for i in (0, 1, 77, 300, 511):
+            X, F, t = b[i].get_state()
+            Xs, Fs, ts = _standalone(apo, runs[i], 5)
+            assert np.array_equal(X, Xs) and np.array_equal(F, Fs), i
