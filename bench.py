@@ -293,6 +293,38 @@ def batched(torch, apo, args):
     }), flush=True)
 
 
+def np_ablation(torch, apo, args):
+    """Neighbour pairs np = 1, 2, 4, 8 on the single large run (ps 4096,
+    D 100, rotated Rastrigin, FP32, 1000 iterations): throughput and the
+    final best fitness over three seeds (np > 1 gathers 2 np rows per
+    foraging protozoan and enlarges the weighted sums of Eqs. (6), (8))."""
+    import gen
+    rows = {}
+    for npairs in (1, 2, 4, 8):
+        rates, bests = [], []
+        for seed in (1, 2, 3):
+            w = gen.rotated_rastrigin_large(seed=seed)
+            w.np_pairs = npairs
+            with make_handle(apo, w, "fp32") as g:
+                g.run(16)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.run(w.max_iter - 16)
+                torch.cuda.synchronize()
+                rates.append(w.pop * (w.max_iter - 16) / (time.perf_counter() - t0))
+                bests.append(g.best()[1])
+        rows[f"np{npairs}"] = {"evals_per_s_median": sorted(rates)[1],
+                               "final_best_f": bests, "final_best_f_median": sorted(bests)[1]}
+    print(json.dumps({
+        "metric": "np ablation: fitness evals/sec and final best fitness, ps 4096 D 100",
+        "value": rows["np1"]["evals_per_s_median"], "unit": "evals/s", "n_gpus": 1,
+        "steps": 984, "warmup": 16, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rotated_rastrigin_ps4096_d100_fp32", "np": [1, 2, 4, 8],
+                   "seeds": [1, 2, 3]},
+        "per_np": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,7 +333,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c1", "c3", "elem-large", "otsu", "c4"])
+                    choices=["c2", "c1", "c3", "elem-large", "otsu", "c4", "np-ablation"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
@@ -335,6 +367,9 @@ def main():
         return
     if args.workload == "c4":
         batched(torch, apo, args)
+        return
+    if args.workload == "np-ablation":
+        np_ablation(torch, apo, args)
         return
     w, precision = workload(args.workload, args.seed)
     steps = w.max_iter if args.steps is None else args.steps

@@ -72,7 +72,10 @@ typedef struct {
 } apo_objective;
 
 enum {
-    APO_FLAG_TRACE = 1u       /* keep every candidate of the last step for apo_get_trace */
+    APO_FLAG_TRACE = 1u,      /* keep every candidate of the last step for apo_get_trace */
+    APO_FLAG_PDR_PLUS = 2u    /* Eq. (13) with the opposite sign before the cosine (a
+                                 variant of the printed formula: the worst ranks of Dr,
+                                 not the best, are the likeliest to go dormant)       */
 };
 
 typedef struct {

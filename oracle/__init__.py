@@ -27,7 +27,7 @@ class _Problem(C.Structure):
         ("pf_max", C.c_double), ("seed", C.c_uint64), ("run", C.c_uint32), ("kind", C.c_int32),
         ("lb", C.POINTER(C.c_double)), ("ub", C.POINTER(C.c_double)),
         ("shift", C.POINTER(C.c_double)), ("rot", C.POINTER(C.c_double)),
-        ("hist", C.POINTER(C.c_uint64)),
+        ("hist", C.POINTER(C.c_uint64)), ("pdr_plus", C.c_int32),
     ]
 
 
@@ -159,6 +159,7 @@ class Problem:
     shift: Optional[np.ndarray] = None
     rot: Optional[np.ndarray] = None
     hist: Optional[np.ndarray] = None
+    pdr_plus: bool = False          # Eq. (13) with the opposite sign (a variant)
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -184,6 +185,7 @@ class Problem:
         s.shift = _ptr(self.shift, C.c_double)
         s.rot = _ptr(self.rot, C.c_double)
         s.hist = _ptr(self.hist, C.c_uint64)
+        s.pdr_plus = 1 if self.pdr_plus else 0
         return s
 
     # -- method ---------------------------------------------------------

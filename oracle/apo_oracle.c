@@ -62,6 +62,7 @@ typedef struct {
     const double *shift;    /* [dim] or NULL (o = 0)              */
     const double *rot;      /* [dim*dim] row-major or NULL        */
     const uint64_t *hist;   /* [256] for Kapur / Otsu             */
+    int32_t pdr_plus;       /* 1: Eq. (13) with the opposite sign  */
 } oracle_problem;
 
 /* Optional per-step record, every array indexed by protozoan id except
@@ -525,7 +526,11 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
 
         if (in_subset((uint32_t)r, (uint32_t)ps, (uint32_t)m_dr, dr_keys)) {
             /* Eq. (13) */
-            double p_dr = 0.5 * (1.0 - cos((1.0 - (double)i / (double)ps) * OR_PI));
+            /* Eq. (13) as printed; the variant flips the sign in front of
+             * the cosine (the reading that makes the worst ranks, not the
+             * best, the likeliest to go dormant) */
+            double c_dr = cos((1.0 - (double)i / (double)ps) * OR_PI);
+            double p_dr = p->pdr_plus ? 0.5 * (1.0 + c_dr) : 0.5 * (1.0 - c_dr);
             if (p_dr > u_op) {
                 /* dormancy, Eq. (1): a fresh protozoan in the bounds */
                 op = OR_DORMANCY;

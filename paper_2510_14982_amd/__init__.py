@@ -16,7 +16,8 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import (APO_E_DONE, APO_FLAG_TRACE, APO_FP32, APO_FP64, KINDS, OPS, APOError,
+from ._lib import (APO_E_DONE, APO_FLAG_PDR_PLUS, APO_FLAG_TRACE, APO_FP32, APO_FP64, KINDS,
+                   OPS, APOError,
                    BatchOptions, Objective, Options, RunDesc, _check, _dptr, lib, strerror)
 
 __all__ = ["APO", "APOError", "Batch", "histogram_u8", "workspace_bytes", "lib", "strerror",
@@ -68,7 +69,7 @@ class APO:
 
     def __init__(self, dim, lb, ub, pop, np_pairs=1, pf_max=0.1, seed=1, max_iter=100,
                  precision="fp64", kind="sphere", shift=None, rot=None, hist=None, run_id=0,
-                 trace=False, stream=None):
+                 trace=False, stream=None, pdr_plus=False):
         torch = _torch()
         self.dim, self.pop, self.max_iter = int(dim), int(pop), int(max_iter)
         self.precision = precision
@@ -77,7 +78,7 @@ class APO:
         shift = None if shift is None else np.ascontiguousarray(shift, np.float64).reshape(self.dim)
         rot = None if rot is None else np.ascontiguousarray(rot, np.float64).reshape(self.dim, self.dim)
         hist = None if hist is None else np.ascontiguousarray(hist, np.uint64).reshape(256)
-        flags = APO_FLAG_TRACE if trace else 0
+        flags = (APO_FLAG_TRACE if trace else 0) | (APO_FLAG_PDR_PLUS if pdr_plus else 0)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         o = _options(max_iter, precision, kind, shift, rot, hist, run_id, flags)
         nbytes = int(lib().apo_workspace_bytes(self.dim, self.pop, int(np_pairs), C.byref(o)))

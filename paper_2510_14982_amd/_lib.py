@@ -20,6 +20,7 @@ APO_OK, APO_E_INVAL, APO_E_NOMEM, APO_E_DEVICE, APO_E_DONE, APO_E_STATE, APO_E_U
 APO_FP64, APO_FP32 = 0, 1
 KINDS = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ackley": 3, "kapur": 4, "otsu": 5}
 APO_FLAG_TRACE = 1
+APO_FLAG_PDR_PLUS = 2
 OPS = {0: "dormancy", 1: "reproduction", 2: "autotroph", 3: "heterotroph"}
 
 

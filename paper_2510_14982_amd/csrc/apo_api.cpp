@@ -548,8 +548,10 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         fsc[t] = 1.0 + std::cos(((double)t / (double)T) * kPi);
         cn[t] = 1.0 - (double)t / (double)T;
     }
-    for (int r = 0; r < pop; ++r)
-        pdr[r] = 0.5 * (1.0 - std::cos((1.0 - (double)(r + 1) / (double)pop) * kPi));
+    for (int r = 0; r < pop; ++r) {
+        const double c = std::cos((1.0 - (double)(r + 1) / (double)pop) * kPi);
+        pdr[r] = (opt->flags & APO_FLAG_PDR_PLUS) ? 0.5 * (1.0 + c) : 0.5 * (1.0 - c);
+    }
 
     std::vector<unsigned char> vlb, vub, vsh, vrot;
     if (h->fp64) {

@@ -39,7 +39,7 @@ def need_gpu():
 
 def make_pair(apo, *, dim, pop, kind="rastrigin", precision="fp64", rotated=False, np_pairs=1,
               pf_max=0.1, seed=1, max_iter=100, lb=-100.0, ub=100.0, shift=True, hist=None,
-              trace=True, run_id=0):
+              trace=True, run_id=0, pdr_plus=False):
     dt = np.float32 if precision == "fp32" else np.float64
     lbv = np.broadcast_to(np.asarray(lb, np.float64), (dim,)).astype(dt).astype(np.float64)
     ubv = np.broadcast_to(np.asarray(ub, np.float64), (dim,)).astype(dt).astype(np.float64)
@@ -53,9 +53,10 @@ def make_pair(apo, *, dim, pop, kind="rastrigin", precision="fp64", rotated=Fals
             M = gen.rotation_matrix(dim, seed, dtype=dt)
     g = apo.APO(dim, lbv, ubv, pop, np_pairs=np_pairs, pf_max=pf_max, seed=seed, max_iter=max_iter,
                 precision=precision, kind=kind, shift=o, rot=M, hist=hist, trace=trace,
-                run_id=run_id)
+                run_id=run_id, pdr_plus=pdr_plus)
     p = O.Problem(dim=dim, pop=pop, lb=lbv, ub=ubv, np_pairs=np_pairs, max_iter=max_iter,
-                  pf_max=pf_max, seed=seed, run_id=run_id, kind=kind, shift=o, rot=M, hist=hist)
+                  pf_max=pf_max, seed=seed, run_id=run_id, kind=kind, shift=o, rot=M, hist=hist,
+                  pdr_plus=pdr_plus)
     return g, p
 
 

@@ -22,6 +22,8 @@ STEP_CASES = [
     ("no_dr", dict(dim=8, pop=17, kind="sphere", pf_max=0.0), 4, 10),
     ("all_dr", dict(dim=8, pop=17, kind="sphere", pf_max=1.0), 4, 10),
     ("pop2_dim1", dict(dim=1, pop=2, kind="rastrigin"), 1, 3),
+    # Eq. (13) with the opposite sign (a variant of the printed formula)
+    ("pdr_plus_variant", dict(dim=12, pop=40, kind="rastrigin", pf_max=1.0, pdr_plus=True), 3, 10),
     ("rotated_rastrigin_fp64", dict(dim=20, pop=70, kind="rastrigin", rotated=True), 3, 50),
     ("rotated_rosenbrock_np3_fp64", dict(dim=33, pop=40, kind="rosenbrock", rotated=True,
                                          np_pairs=3), 2, 20),

@@ -143,6 +143,37 @@ def test_dormancy_probability_follows_eq13():
     assert best_dorm >= best_n - 1
 
 
+def test_dormancy_variant_mirrors_eq13():
+    """The opposite sign in Eq. (13) (a variant): p_dr = (1 + cos((1 - i/ps)
+    pi)) / 2 is exactly 1 for the worst rank and ~0 for the best, so in Dr
+    the worst rank always goes dormant and the best almost never does; the
+    variant and the printed form add up to 1 at every rank."""
+    p, X, F = _state(pop=16, pf_max=1.0, T=10)
+    p.pdr_plus = True
+    best_n = best_dorm = worst_n = worst_dorm = 0
+    for seed in range(1, 400):
+        p.seed = seed
+        _, _, tr = p.step(3, X, F)
+        b, w = tr.op[tr.perm[0]], tr.op[tr.perm[-1]]
+        if b in (DORM, REPRO):
+            best_n += 1
+            best_dorm += b == DORM
+        if w in (DORM, REPRO):
+            worst_n += 1
+            worst_dorm += w == DORM
+    assert best_n > 20 and worst_n > 20
+    assert worst_dorm == worst_n
+    assert best_dorm <= 2
+    # same draws, opposite decisions wherever u_op lies between the two forms
+    p.seed = 5
+    p.pdr_plus = False
+    _, _, a = p.step(3, X, F)
+    p.pdr_plus = True
+    _, _, b = p.step(3, X, F)
+    dr = np.isin(a.op, (DORM, REPRO))
+    assert np.array_equal(dr, np.isin(b.op, (DORM, REPRO)))   # Dr itself is unchanged
+
+
 def test_dormancy_ignores_the_row_and_reproduction_keeps_unmasked_dims():
     p, X, F = _state(pop=16, pf_max=1.0)
     X2 = gen.random_state(16, 6, p.lb, p.ub, seed=99)
