@@ -46,7 +46,14 @@ typedef enum {
 
 typedef enum {
     APO_FP64 = 0,            /* positions and fitness in binary64 */
-    APO_FP32 = 1             /* positions and fitness in binary32 */
+    APO_FP32 = 1,            /* positions and fitness in binary32 */
+    APO_BF16 = 2             /* rotated objectives only: binary32 state; z = M (x - o)
+                                estimated on the matrix cores with BF16 operands and
+                                binary32 accumulation, every candidate the estimate
+                                cannot settle under a rigorous bound (and every
+                                acceptance) re-scored in binary32, so the run equals
+                                the binary32 form's; apo_best re-scores the elite in
+                                binary64 */
 } apo_precision;
 
 typedef enum {

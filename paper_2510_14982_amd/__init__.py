@@ -16,7 +16,8 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import (APO_E_DONE, APO_FLAG_PDR_PLUS, APO_FLAG_TRACE, APO_FP32, APO_FP64, KINDS,
+from ._lib import (APO_BF16, APO_E_DONE, APO_FLAG_PDR_PLUS, APO_FLAG_TRACE, APO_FP32, APO_FP64,
+                   KINDS,
                    OPS, APOError,
                    BatchOptions, Objective, Options, RunDesc, _check, _dptr, lib, strerror)
 
@@ -35,7 +36,7 @@ def _options(max_iter, precision, kind, shift, rot, hist, run_id, flags, stream=
              workspace=None, workspace_bytes=0):
     o = Options()
     o.max_iter = int(max_iter)
-    o.precision = APO_FP32 if precision in ("fp32", APO_FP32) else APO_FP64
+    o.precision = {"fp64": APO_FP64, "fp32": APO_FP32, "bf16": APO_BF16}.get(precision, precision)
     o.objective.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
     o.objective.shift = _dptr(shift)
     o.objective.rot = _dptr(rot)

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libapo.so")
 
 APO_OK, APO_E_INVAL, APO_E_NOMEM, APO_E_DEVICE, APO_E_DONE, APO_E_STATE, APO_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-APO_FP64, APO_FP32 = 0, 1
+APO_FP64, APO_FP32, APO_BF16 = 0, 1, 2
 KINDS = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ackley": 3, "kapur": 4, "otsu": 5}
 APO_FLAG_TRACE = 1
 APO_FLAG_PDR_PLUS = 2

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libapo.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["apo_kernels.hip", "apo_step_elem_f32.hip", "apo_step_elem_f64.hip",
-           "apo_step_tile_f32.hip", "apo_step_tile_f64.hip", "apo_api.cpp"]
+           "apo_step_tile_f32.hip", "apo_step_tile_f64.hip", "apo_gemm.hip", "apo_api.cpp"]
 
 
 def hipcc() -> str:

@@ -25,12 +25,21 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Offsets of every device array inside the workspace (bytes, 256-aligned).
 struct Layout {
+    size_t gYr, gAb, gan, gP1, gP2, glist, gcount, gMb, gMf, gMd, go64;   // GEMM form
+    int Kp, Np;
     size_t X[2], F, perm, Fs, drf, ctrl, p_ah, fscale, cnear, p_dr, lb, ub, shift, rotp, htab, hist,
         best, trY, trF, trOp, total;
     int Dp, Nt, Ks;
 };
 
 bool is_threshold(int kind) { return kind == apok::K_KAPUR || kind == apok::K_OTSU; }
+
+// The GEMM form serves rotated objectives of large dimension in binary32 and
+// every BF16 handle.
+bool gemm_form(int dim, const apo_options &o) {
+    if (!o.objective.rot || is_threshold(o.objective.kind)) return false;
+    return o.precision == APO_BF16 || (o.precision == APO_FP32 && dim > 512);
+}
 
 Layout make_layout(int dim, int pop, const apo_options &o) {
     Layout L;
@@ -60,7 +69,24 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     L.lb = take((size_t)L.Dp * es);
     L.ub = take((size_t)L.Dp * es);
     L.shift = take((size_t)L.Dp * es);
-    L.rotp = o.objective.rot ? take((size_t)L.Ks * L.Nt * 64 * es) : 0;
+    const bool gf = gemm_form(dim, o);
+    L.rotp = (o.objective.rot && !gf) ? take((size_t)L.Ks * L.Nt * 64 * es) : 0;
+    if (gf) {
+        L.Kp = (dim + 63) / 64 * 64;
+        L.Np = (dim + 127) / 128 * 128;
+        const bool bf = o.precision == APO_BF16;
+        L.gYr = take((size_t)pop * L.Dp * 4);
+        L.gAb = bf ? take((size_t)pop * L.Kp * 2) : 0;
+        L.gan = bf ? take((size_t)pop * 4) : 0;
+        L.gP1 = take((size_t)pop * (L.Np / 64) * 4);
+        L.gP2 = take((size_t)pop * (L.Np / 64) * 4);
+        L.glist = take((size_t)pop * 4);
+        L.gcount = take(4);
+        L.gMb = bf ? take((size_t)L.Np * L.Kp * 2) : 0;
+        L.gMf = take((size_t)L.Np * L.Kp * 4);
+        L.gMd = take((size_t)dim * dim * 8);
+        L.go64 = take((size_t)dim * 8);
+    }
     L.htab = is_threshold(o.objective.kind) ? take(3 * 257 * 8) : 0;
     L.hist = is_threshold(o.objective.kind) ? take(256 * 8) : 0;
     L.best = take((size_t)(dim + 1) * 8);
@@ -79,9 +105,11 @@ int check_args(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     if (dim < 1 || pop < 2 || np < 1 || np > apok::kMaxNp) return APO_E_INVAL;
     if (!(pf_max >= 0.0 && pf_max <= 1.0)) return APO_E_INVAL;
     if (opt->max_iter < 1) return APO_E_INVAL;
-    if (opt->precision != APO_FP64 && opt->precision != APO_FP32) return APO_E_INVAL;
+    if (opt->precision != APO_FP64 && opt->precision != APO_FP32 && opt->precision != APO_BF16)
+        return APO_E_INVAL;
     const int kind = opt->objective.kind;
     if (kind < APO_SPHERE || kind > APO_OTSU) return APO_E_INVAL;
+    if (opt->precision == APO_BF16 && !opt->objective.rot) return APO_E_INVAL;
     for (int d = 0; d < dim; ++d)
         if (!std::isfinite(lb[d]) || !std::isfinite(ub[d]) || !(lb[d] < ub[d])) return APO_E_INVAL;
     if (is_threshold(kind)) {
@@ -102,7 +130,10 @@ int check_args(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     // sizes the kernels are built for
     if (pop > kMaxPop) return APO_E_UNSUPPORTED;
     const bool tile = opt->objective.rot != nullptr || is_threshold(kind);
-    if (tile) {
+    if (gemm_form(dim, *opt)) {
+        // separable objectives only (the row sums are taken per column tile)
+        if (kind == APO_ROSENBROCK || apok::chunks_for_dim(dim) < 0) return APO_E_UNSUPPORTED;
+    } else if (tile) {
         const int lim = is_threshold(kind) ? 512 : (opt->precision == APO_FP64 ? 256 : 512);
         if (dim > lim) return APO_E_UNSUPPORTED;
     } else if (apok::chunks_for_dim(dim) < 0) {
@@ -233,6 +264,7 @@ int batch_layout(int32_t n, const apo_run_desc *runs, BatchLayout &B) {
         if (d.opt.stream || d.opt.workspace || d.opt.workspace_bytes) return APO_E_INVAL;
         const int chk = check_args(d.dim, d.lb, d.ub, d.pop, d.np, d.pf_max, &d.opt);
         if (chk != APO_OK) return chk;
+        if (gemm_form(d.dim, d.opt)) return APO_E_UNSUPPORTED;   // not in batches
         const Layout L = make_layout(d.dim, d.pop, d.opt);
         B.run_off[i] = off;
         B.run_bytes[i] = L.total;
@@ -460,6 +492,7 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     if (chk != APO_OK) return chk;
     const Layout L = make_layout(dim, pop, *opt);
     if (opt->workspace && opt->workspace_bytes < L.total) return APO_E_INVAL;
+    const bool gf = gemm_form(dim, *opt);
 
     apo_t *h = new (std::nothrow) apo_t();
     if (!h) return APO_E_NOMEM;
@@ -508,6 +541,7 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         p.rows = (wide > 16 && pop >= 256 * wide) ? wide : 16;
     }
     p.rank_lds = pop <= 256 ? 1 : 0;   // one workgroup ranks the whole run
+    p.gemm = gf ? 1 : 0;
     p.trace = (opt->flags & APO_FLAG_TRACE) ? 1 : 0;
     p.seed_lo = (uint32_t)(seed & 0xFFFFFFFFu);
     p.seed_hi = (uint32_t)(seed >> 32);
@@ -529,7 +563,24 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     p.lb = ws + L.lb;
     p.ub = ws + L.ub;
     p.shift = ws + L.shift;
-    p.rotp = p.rotated ? ws + L.rotp : nullptr;
+    p.rotp = (p.rotated && !gf) ? ws + L.rotp : nullptr;
+    if (gf) {
+        apok::GemmBufs &g = p.gb;
+        g.Yr = (float *)(ws + L.gYr);
+        g.Ab = L.gAb ? (uint16_t *)(ws + L.gAb) : nullptr;
+        g.anorm = L.gan ? (float *)(ws + L.gan) : nullptr;
+        g.P1 = (float *)(ws + L.gP1);
+        g.P2 = (float *)(ws + L.gP2);
+        g.list = (int32_t *)(ws + L.glist);
+        g.count = (int32_t *)(ws + L.gcount);
+        g.Mb = L.gMb ? (const uint16_t *)(ws + L.gMb) : nullptr;
+        g.Mf = (const float *)(ws + L.gMf);
+        g.Md = (const double *)(ws + L.gMd);
+        g.o64 = (const double *)(ws + L.go64);
+        g.Kp = L.Kp;
+        g.Np = L.Np;
+        g.bf16 = opt->precision == APO_BF16 ? 1 : 0;
+    }
     p.htab = is_threshold(p.kind) ? (const double *)(ws + L.htab) : nullptr;
     if (p.trace) {
         p.trY = ws + L.trY;
@@ -563,7 +614,31 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         to_device_row<float>(vub, ub, dim, L.Dp);
         to_device_row<float>(vsh, opt->objective.shift, dim, L.Dp);
     }
-    if (p.rotated) {
+    std::vector<unsigned char> gmb, gmf, gmd, go;
+    if (gf) {
+        // M rows padded to [Np][Kp] in binary32 and BF16 (round to nearest
+        // even), and M and o in binary64 for the elite
+        const double *M = opt->objective.rot;
+        gmf.assign((size_t)L.Np * L.Kp * 4, 0);
+        gmd.assign((size_t)dim * dim * 8, 0);
+        go.assign((size_t)dim * 8, 0);
+        float *mf = reinterpret_cast<float *>(gmf.data());
+        for (int n = 0; n < dim; ++n)
+            for (int k = 0; k < dim; ++k) mf[(size_t)n * L.Kp + k] = (float)M[(size_t)n * dim + k];
+        std::memcpy(gmd.data(), M, (size_t)dim * dim * 8);
+        if (opt->objective.shift) std::memcpy(go.data(), opt->objective.shift, (size_t)dim * 8);
+        if (p.gb.bf16) {
+            gmb.assign((size_t)L.Np * L.Kp * 2, 0);
+            uint16_t *mb = reinterpret_cast<uint16_t *>(gmb.data());
+            for (size_t i = 0; i < (size_t)L.Np * L.Kp; ++i) {
+                uint32_t u;
+                std::memcpy(&u, &mf[i], 4);
+                u += 0x7FFFu + ((u >> 16) & 1u);   // finite entries of an orthogonal M
+                mb[i] = (uint16_t)(u >> 16);
+            }
+        }
+    }
+    if (p.rotated && !gf) {
         // B fragments of M^T for v_mfma 16x16x4: block (ks, nt), lane l holds
         // B[k][n] = M[n][k] with k = Ks (l / 16) + ks, n = 16 nt + l % 16
         // (the kernel reads A in the same k order).
@@ -600,8 +675,15 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     CREATE_HIP(hipMemcpyAsync(ws + L.lb, vlb.data(), vlb.size(), hipMemcpyHostToDevice, s));
     CREATE_HIP(hipMemcpyAsync(ws + L.ub, vub.data(), vub.size(), hipMemcpyHostToDevice, s));
     CREATE_HIP(hipMemcpyAsync(ws + L.shift, vsh.data(), vsh.size(), hipMemcpyHostToDevice, s));
-    if (p.rotated)
+    if (p.rotated && !gf)
         CREATE_HIP(hipMemcpyAsync(ws + L.rotp, vrot.data(), vrot.size(), hipMemcpyHostToDevice, s));
+    if (gf) {
+        CREATE_HIP(hipMemcpyAsync(ws + L.gMf, gmf.data(), gmf.size(), hipMemcpyHostToDevice, s));
+        CREATE_HIP(hipMemcpyAsync(ws + L.gMd, gmd.data(), gmd.size(), hipMemcpyHostToDevice, s));
+        CREATE_HIP(hipMemcpyAsync(ws + L.go64, go.data(), go.size(), hipMemcpyHostToDevice, s));
+        if (p.gb.bf16)
+            CREATE_HIP(hipMemcpyAsync(ws + L.gMb, gmb.data(), gmb.size(), hipMemcpyHostToDevice, s));
+    }
     if (is_threshold(p.kind)) {
         CREATE_HIP(hipMemcpyAsync(ws + L.hist, opt->objective.hist, 256 * 8, hipMemcpyHostToDevice, s));
         CREATE_HIP(apok::launch_hist_tables(p, (const uint64_t *)(ws + L.hist), s));
@@ -744,6 +826,8 @@ int apo_best(apo_t *h, double *x_out, double *f_out, int64_t *fes_out) {
     double *d_best = (double *)(h->ws + h->L.best);
     std::vector<double> row((size_t)h->dim + 1);
     APO_HIP(h, apok::launch_best(h->p, h->fp64, h->t & 1, d_best, h->stream));
+    if (h->p.gemm)   // the elite's fitness re-scored in binary64
+        APO_HIP(h, apok::launch_elite_f64(h->p, h->p.gb, d_best + 1, d_best, h->stream));
     APO_HIP(h, hipMemcpyAsync(row.data(), d_best, row.size() * 8, hipMemcpyDeviceToHost, h->stream));
     APO_HIP(h, hipStreamSynchronize(h->stream));
     if (f_out) *f_out = row[0];

@@ -1,0 +1,484 @@
+// apo_gemm.hip -- the GEMM form of the step for rotated objectives of large
+// dimension (binary32 state): per iteration
+//   candidates  -> Yr [ps][Dp] (rank order) and A = bf16(y - o) [ps][Kp]
+//   Z = A M^T on the matrix cores, 128 x 128 output tiles, with the
+//                  objective's row sums fused into the epilogue (partials)
+//   selection   -> strict greedy choice, rows written to the next buffer.
+// With bfloat16 (BF16) operands the product is a cheap estimate: each
+// candidate whose comparison with its parent the estimate cannot settle
+// under a rigorous error bound -- and every certain acceptance -- is
+// re-scored by the same binary32 product on the listed rows, so every stored
+// fitness equals the binary32 form's.  The elite's final fitness is
+// re-scored in binary64.
+#include "apo_step.hpp"
+
+namespace apok {
+
+constexpr int kGM = 128, kGN = 128;      // output tile of a workgroup
+constexpr int kGRowB = 128;              // bytes of K per row and chunk
+constexpr int kGLds = kGRowB + 16;       // LDS row stride in bytes
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// One product launch: rows are list slots (list != nullptr: slot k is rank
+// list[k], *count slots) or ranks (rows of them).
+struct GemmRun {
+    const uint16_t *Ab;   // BF16 A rows [pop][Kp], or nullptr: A = y - o from Yr
+    const float *Yr;      // [pop][Dp]
+    const float *o;       // [Dp]
+    const void *B;        // M rows [Np][Kp] (BF16 or binary32)
+    const int32_t *list;
+    const int32_t *count;
+    int rows, D, Dp, Kp, Np, kind;
+    float *P1, *P2;       // [slot][Np / 64]
+};
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {   // round to nearest even
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Candidates of one iteration (or of the initial population), by rank.
+// ---------------------------------------------------------------------------
+template <int G, int NCH, int NPMAX, bool BF16>
+__global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init) {
+    typedef float T;
+    const int lane = threadIdx.x & (G - 1);
+    const int item = (blockIdx.x * 256 + threadIdx.x) / G;
+    if (!init && blockIdx.x == 0 && threadIdx.x == 0) *w.count = 0;   // rescore list
+    if (item >= p.pop) return;
+    const int D = p.dim, Dp = p.Dp;
+    const Iter it = load_iter(p, init);
+    const int t = it.t;
+    const T *Xc = (const T *)p.X[(t + 1) & 1];
+    constexpr int MW = (4 * G * NCH + 31) / 32;
+    __shared__ uint32_t mwords[256 / G][MW];
+    Plan<T, NPMAX> c;
+    Rows<T, NCH> rw;
+    if (init) {
+        c.op = OP_DORMANCY; c.id = item; c.r = item; c.m = (uint32_t)D; c.fold = T(0);
+    } else {
+        Draws<T> d;
+        plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
+        uniform_draws<G>(d);
+        plan_decide<T, NPMAX>(p, item, it, d, c);
+        plan_pairs<T, NPMAX>(p, item, t, d, c);
+        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, false, rw);
+        plan_mask<T, NPMAX, G>(p, c, mwords[threadIdx.x / G], lane);
+    }
+    const T *o = (const T *)p.shift;
+    float *yrow = w.Yr + (size_t)item * Dp;
+    uint16_t *arow = BF16 ? w.Ab + (size_t)item * w.Kp : nullptr;
+    float ss = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int d0 = 4 * (lane + ch * G);
+        if (d0 < D) {
+            T y[4], ov[4];
+            candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, rw.x[ch], rw.xj[ch], rw.am[ch],
+                                 rw.ap[ch], rw.am[ch], rw.ap[ch], y);
+            load4(o + d0, ov);
+            store4(yrow + d0, y);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float a = d0 + e < D ? y[e] - ov[e] : 0.f;
+                ss += a * a;
+                if (BF16) arow[d0 + e] = to_bf16(a);
+            }
+        }
+    }
+    if (BF16) {
+        ss = group_sum<G>(ss);
+        if (lane == 0) w.anorm[item] = sqrtf(ss);
+    }
+    if (p.trace && !init && lane == 0) p.trOp[c.id] = c.op;
+}
+
+// One chunk (128 bytes of K) of a loader thread's A and B rows into
+// registers: B from the packed M rows; A either stored (BF16) or y - o.
+struct GemmChunk {
+    uint4 a0, a1, a2, a3, b0, b1, b2, b3;
+};
+
+template <typename TA>
+__device__ __forceinline__ GemmChunk gemm_fetch(const GemmRun &g, const unsigned char *Bp,
+                                                int arow, bool live, int lh, int kc) {
+    constexpr int ES = sizeof(TA);
+    GemmChunk c;
+    uint4 ra[4];
+    const uint4 *bp = (const uint4 *)(Bp + (size_t)kc * ES);
+    c.b0 = bp[0];
+    c.b1 = bp[1];
+    c.b2 = bp[2];
+    c.b3 = bp[3];
+    if (ES == 2) {
+        const uint4 *ap =
+            (const uint4 *)((const unsigned char *)g.Ab + ((size_t)arow * g.Kp + kc) * 2 + lh * 64);
+        const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = live ? ap[q] : zero4;
+    } else {
+        const int k0 = kc + lh * 16;
+        const float *yr = g.Yr + (size_t)arow * g.Dp;
+        if (live && k0 + 16 <= g.D) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 y4 = ((const float4 *)(yr + k0))[q];
+                const float4 o4 = ((const float4 *)(g.o + k0))[q];
+                ra[q] = make_uint4(__float_as_uint(y4.x - o4.x), __float_as_uint(y4.y - o4.y),
+                                   __float_as_uint(y4.z - o4.z), __float_as_uint(y4.w - o4.w));
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = k0 + 4 * q + e;
+                    v[e] = (live && k < g.D) ? yr[k] - g.o[k] : 0.f;
+                }
+                ra[q] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]),
+                                   __float_as_uint(v[2]), __float_as_uint(v[3]));
+            }
+        }
+    }
+    c.a0 = ra[0];
+    c.a1 = ra[1];
+    c.a2 = ra[2];
+    c.a3 = ra[3];
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Z = A M^T with the objective's per-row sums over each 64-column half tile
+// (P1: the summed terms, or sum z^2 for Ackley; P2: sum cos 2 pi z for
+// Ackley, sum z^2 otherwise).  Rows are list slots (the ranks of a rescore
+// list) or ranks.  TA = uint16_t (BF16 bits, A read from Ab) or float (A =
+// y - o computed from Yr while loading).  Workgroup: 4 wavefronts, each a
+// 64 x 64 quadrant of 4 x 4 MFMA 16 x 16 tiles; K in chunks of 128 bytes
+// per row, the next chunk fetched into registers during the MFMA work.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
+    constexpr int ES = sizeof(TA), KC = kGRowB / ES, KSUB = ES == 2 ? 16 : 4;
+    __shared__ __align__(16) unsigned char sA[kGM * kGLds];
+    __shared__ __align__(16) unsigned char sB[kGN * kGLds];
+    const int nrows = g.list ? *g.count : g.rows;
+    const int m0 = blockIdx.y * kGM;
+    if (m0 >= nrows) return;   // the whole workgroup: no barrier is skipped
+    const int n0 = blockIdx.x * kGN;
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+    const int lr = tid >> 1, lh = tid & 1;                  // loader: row, 64-byte half
+    const int slot = m0 + lr;
+    const bool live = slot < nrows;
+    const int arow = live ? (g.list ? g.list[slot] : slot) : 0;
+    const unsigned char *Bp = (const unsigned char *)g.B + (size_t)(n0 + lr) * g.Kp * ES + lh * 64;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int wr = 64 * (wave >> 1), wc = 64 * (wave & 1);
+    GemmChunk ch = gemm_fetch<TA>(g, Bp, arow, live, lh, 0);
+    for (int kc = 0; kc < g.Kp; kc += KC) {
+        __syncthreads();   // the previous chunk's readers are done
+        uint4 *da = (uint4 *)(sA + lr * kGLds + lh * 64), *db = (uint4 *)(sB + lr * kGLds + lh * 64);
+        da[0] = ch.a0; da[1] = ch.a1; da[2] = ch.a2; da[3] = ch.a3;
+        db[0] = ch.b0; db[1] = ch.b1; db[2] = ch.b2; db[3] = ch.b3;
+        __syncthreads();
+        if (kc + KC < g.Kp)   // in flight during the MFMA work
+            ch = gemm_fetch<TA>(g, Bp, arow, live, lh, kc + KC);
+#pragma unroll
+        for (int ks = 0; ks < KC / KSUB; ++ks) {
+            if (ES == 2) {
+                // 16 x 16 x 16 BF16: lane l holds A[l % 16][4 (l / 16) .. + 3]
+                // and B[4 (l / 16) .. + 3][l % 16]
+                const int kb = (ks * 16 + 4 * (l >> 4)) * 2;
+                s16x4 a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    a[i] = *(const s16x4 *)(sA + (wr + 16 * i + (l & 15)) * kGLds + kb);
+                    b[i] = *(const s16x4 *)(sB + (wc + 16 * i + (l & 15)) * kGLds + kb);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j],
+                                                                             0, 0, 0);
+            } else {
+                // 16 x 16 x 4 FP32: lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
+                const int kb = (ks * 4 + (l >> 4)) * 4;
+                float a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    a[i] = *(const float *)(sA + (wr + 16 * i + (l & 15)) * kGLds + kb);
+                    b[i] = *(const float *)(sB + (wc + 16 * i + (l & 15)) * kGLds + kb);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0,
+                                                                        0, 0);
+            }
+        }
+    }
+    // epilogue: element v of lane l in tile (i, j) is Z[row 4 (l / 16) + v][col l % 16]
+    const int half = (n0 + wc) / 64, NH = g.Np / 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float g1 = 0.f, g2 = 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int col = n0 + wc + 16 * j + (l & 15);
+                if (col < g.D) {
+                    const float z = acc[i][j][v];
+                    const float zz = z * z;
+                    if (g.kind == K_RASTRIGIN) {
+                        g1 += zz - 10.f * cos2pi(z) + 10.f;
+                        g2 += zz;
+                    } else if (g.kind == K_ACKLEY) {
+                        g1 += zz;
+                        g2 += cos2pi(z);
+                    } else {
+                        g1 += zz;
+                        g2 += zz;
+                    }
+                }
+            }
+            g1 = group_sum<16>(g1);
+            g2 = group_sum<16>(g2);
+            const int srow = m0 + wr + 16 * i + 4 * (l >> 4) + v;
+            if ((l & 15) == 0 && srow < nrows) {
+                g.P1[(size_t)srow * NH + half] = g1;
+                g.P2[(size_t)srow * NH + half] = g2;
+            }
+        }
+    }
+}
+
+// Objective of a row from its partial sums (fixed order).
+__device__ __forceinline__ void row_sums(const GemmRun &g, int slot, float &s1, float &s2) {
+    const int NH = g.Np / 64;
+    s1 = 0.f;
+    s2 = 0.f;
+    for (int h = 0; h < NH; ++h) {
+        s1 += g.P1[(size_t)slot * NH + h];
+        s2 += g.P2[(size_t)slot * NH + h];
+    }
+}
+
+__device__ __forceinline__ float row_objective(int kind, int D, float s1, float s2) {
+    if (kind == K_ACKLEY)
+        return -20.f * expf(-0.2f * sqrtf(s1 / (float)D)) - expf(s2 / (float)D) + 20.f +
+               (float)kE;
+    return s1;
+}
+
+// Copies a row of D floats (one wavefront).
+__device__ __forceinline__ void copy_row(float *dst, const float *src, int D, int l) {
+    for (int d0 = 4 * l; d0 < D; d0 += 256) {
+        if (d0 + 4 <= D) {
+            *(float4 *)(dst + d0) = *(const float4 *)(src + d0);
+        } else {
+            for (int d = d0; d < D; ++d) dst[d] = src[d];
+        }
+    }
+}
+
+// Binary32 selection (one wavefront per slot): rows of the list, or every
+// rank.  Writes the chosen row and fitness of the next buffer.
+__global__ __launch_bounds__(256) void gemm_select(Params p, GemmRun g, GemmBufs w, int init) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int t = init ? 0 : __hip_atomic_load(&p.ctrl->t_next, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (!init && blockIdx.x == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
+    const int nrows = g.list ? *g.count : p.pop;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= nrows) return;
+    const int r = g.list ? g.list[slot] : slot;
+    const int id = init ? r : p.perm[r];
+    float s1, s2;
+    row_sums(g, slot, s1, s2);
+    const float fnew = row_objective(p.kind, p.dim, s1, s2);
+    const float fold = init ? 0.f : ((const float *)p.Fs)[r];
+    const bool accept = init || fnew < fold;
+    const float *X0 = (const float *)p.X[(t + 1) & 1];
+    float *X1 = (float *)p.X[t & 1];
+    const float *y = w.Yr + (size_t)r * p.Dp;
+    copy_row(X1 + (size_t)id * p.Dp, accept ? y : X0 + (size_t)id * p.Dp, p.dim, l);
+    if (l == 0) ((float *)p.F)[id] = accept ? fnew : fold;
+    if (p.trace && !init) {
+        copy_row((float *)p.trY + (size_t)id * p.Dp, y, p.dim, l);
+        if (l == 0) ((float *)p.trF)[id] = fnew;
+    }
+}
+
+// BF16 pass (one wavefront per rank): from the estimate F^ and the bound B
+// on |F^ - F32| (F32 = the binary32 form's value of the same candidate),
+// a candidate with F^ - B >= F_old is certainly rejected (the parent row is
+// carried over); every other candidate goes to the rescore list.
+__global__ __launch_bounds__(256) void gemm_classify(Params p, GemmRun g, GemmBufs w) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + wave;
+    if (r >= p.pop) return;
+    const int t = __hip_atomic_load(&p.ctrl->t_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int id = p.perm[r];
+    const int D = p.dim;
+    float s1, s2;
+    row_sums(g, r, s1, s2);
+    const float fhat = row_objective(p.kind, D, s1, s2);
+    const float fold = ((const float *)p.Fs)[r];
+    // Coordinate error: BF16 operands (unit roundoff 2^-8 each) and two
+    // binary32 accumulations over D terms, times sum_j |M_ij| |a_j| <=
+    // ||a||_2 (orthogonal rows; the BF16 rows' norms stay within 1.01).
+    const float e = (1.01f * 0.0078125f + 2.f * (float)(D + 2) * 5.9604645e-8f) * 1.01f *
+                    w.anorm[r];
+    const float ce = fminf(2.f, 6.2831853f * e);        // |cos 2 pi a - cos 2 pi b| bound
+    const float gD = 2.f * (float)D * 5.9604645e-8f;     // binary32 evaluation of the sums
+    float B;
+    if (p.kind == K_ACKLEY) {
+        const float rr = sqrtf(s1 / (float)D);
+        B = 4.f * e + 2.7182818f * ce + gD * (4.f * rr + 2.7182818f) ;
+    } else {
+        const float zn = sqrtf(s2);                     // ||z^||_2
+        B = 2.f * e * sqrtf((float)D) * zn + (float)D * e * e +
+            (p.kind == K_RASTRIGIN ? 10.f * (float)D * ce : 0.f) +
+            gD * (s2 + (p.kind == K_RASTRIGIN ? 20.f * (float)D : 0.f));
+    }
+    B = B * 1.05f + 1e-6f * (fabsf(fhat) + fabsf(fold));
+    if (fhat - B >= fold) {
+        const float *X0 = (const float *)p.X[(t + 1) & 1];
+        float *X1 = (float *)p.X[t & 1];
+        copy_row(X1 + (size_t)id * p.Dp, X0 + (size_t)id * p.Dp, D, l);
+        if (l == 0) ((float *)p.F)[id] = fold;
+        if (p.trace) {
+            copy_row((float *)p.trY + (size_t)id * p.Dp, w.Yr + (size_t)r * p.Dp, D, l);
+            if (l == 0) ((float *)p.trF)[id] = fhat;
+        }
+    } else if (l == 0) {
+        const int k = atomicAdd(w.count, 1);
+        w.list[k] = r;
+    }
+}
+
+// Binary64 re-score of one row (the elite): z = M (x - o) and the objective
+// in binary64 (one workgroup of 256 threads).  out[0] receives F.
+__global__ __launch_bounds__(256) void elite_f64(Params p, GemmBufs w, const double *x,
+                                                 double *out) {
+    __shared__ double red[2][256];
+    const int D = p.dim;
+    double s1 = 0.0, s2 = 0.0;
+    for (int n = threadIdx.x; n < D; n += 256) {
+        const double *m = w.Md + (size_t)n * D;
+        double z = 0.0;
+        for (int k = 0; k < D; ++k) z += m[k] * (x[k] - w.o64[k]);
+        if (p.kind == K_RASTRIGIN) {
+            s1 += z * z - 10.0 * cos(2.0 * kPi * z) + 10.0;
+        } else if (p.kind == K_ACKLEY) {
+            s1 += z * z;
+            s2 += cos(2.0 * kPi * z);
+        } else {
+            s1 += z * z;
+        }
+    }
+    red[0][threadIdx.x] = s1;
+    red[1][threadIdx.x] = s2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < 256; ++i) {
+            a += red[0][i];
+            b += red[1][i];
+        }
+        out[0] = p.kind == K_ACKLEY
+                     ? -20.0 * exp(-0.2 * sqrt(a / (double)D)) - exp(b / (double)D) + 20.0 + kE
+                     : a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static GemmRun gemm_run(const Params &p, const GemmBufs &w, bool bf16, bool listed) {
+    GemmRun g;
+    g.Ab = bf16 ? w.Ab : nullptr;
+    g.Yr = w.Yr;
+    g.o = (const float *)p.shift;
+    g.B = bf16 ? (const void *)w.Mb : (const void *)w.Mf;
+    g.list = listed ? w.list : nullptr;
+    g.count = w.count;
+    g.rows = p.pop;
+    g.D = p.dim;
+    g.Dp = p.Dp;
+    g.Kp = w.Kp;
+    g.Np = w.Np;
+    g.kind = p.kind;
+    g.P1 = w.P1;
+    g.P2 = w.P2;
+    return g;
+}
+
+template <bool BF16>
+static hipError_t launch_cand(const Params &p, const GemmBufs &w, int init, hipStream_t s) {
+    const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
+    const long long threads = (long long)p.pop * G;
+    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+#define APO_CAND(GG, CC)                                                                     \
+    if (G == GG && NCH == CC) {                                                              \
+        if (p.np == 1)                                                                       \
+            hipLaunchKernelGGL((gemm_cand<GG, CC, 1, BF16>), grid, block, 0, s, p, w, init); \
+        else                                                                                 \
+            hipLaunchKernelGGL((gemm_cand<GG, CC, kMaxNp, BF16>), grid, block, 0, s, p, w,  \
+                               init);                                                        \
+        return hipGetLastError();                                                            \
+    }
+    APO_CAND(4, 1) APO_CAND(8, 1) APO_CAND(16, 1) APO_CAND(32, 1) APO_CAND(64, 1)
+    APO_CAND(64, 2) APO_CAND(64, 4)
+#undef APO_CAND
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_gemm(const GemmRun &g, bool bf16, hipStream_t s) {
+    const dim3 grid((unsigned)(g.Np / kGN), (unsigned)((g.rows + kGM - 1) / kGM)), block(256);
+    if (bf16)
+        hipLaunchKernelGGL(gemm_obj<uint16_t>, grid, block, 0, s, g);
+    else
+        hipLaunchKernelGGL(gemm_obj<float>, grid, block, 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStream_t s) {
+    const bool bf16 = w.bf16 && !init;   // the initial fitness is taken in binary32
+    const dim3 sgrid((unsigned)((p.pop + 3) / 4)), sblock(256);
+    hipError_t e = bf16 ? launch_cand<true>(p, w, init, s) : launch_cand<false>(p, w, init, s);
+    if (e != hipSuccess) return e;
+    if (!bf16) {
+        const GemmRun g = gemm_run(p, w, false, false);
+        if ((e = launch_gemm(g, false, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(gemm_select, sgrid, sblock, 0, s, p, g, w, init);
+        return hipGetLastError();
+    }
+    const GemmRun gb = gemm_run(p, w, true, false);
+    if ((e = launch_gemm(gb, true, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(gemm_classify, sgrid, sblock, 0, s, p, gb, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const GemmRun gf = gemm_run(p, w, false, true);
+    if ((e = launch_gemm(gf, false, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(gemm_select, sgrid, sblock, 0, s, p, gf, w, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_elite_f64(const Params &p, const GemmBufs &w, const double *x, double *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(elite_f64, dim3(1), dim3(256), 0, s, p, w, x, out);
+    return hipGetLastError();
+}
+
+}  // namespace apok

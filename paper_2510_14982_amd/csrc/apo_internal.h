@@ -25,6 +25,24 @@ struct Ctrl {
     int32_t pad[48];
 };
 
+// Buffers of the GEMM form (rotated objectives of large dimension, and the
+// BF16 form): candidates by rank, the product's operands and partial sums,
+// the rescore list and M in the operand precisions.
+struct GemmBufs {
+    float *Yr;            // [pop][Dp] candidates by rank
+    uint16_t *Ab;         // [pop][Kp] BF16 y - o (BF16 form)
+    float *anorm;         // [pop] ||y - o||_2 (BF16 form)
+    float *P1, *P2;       // [pop][Np / 64] partial row sums
+    int32_t *list;        // [pop] ranks to re-score in binary32
+    int32_t *count;       // its length
+    const uint16_t *Mb;   // [Np][Kp] M in BF16
+    const float *Mf;      // [Np][Kp] M in binary32
+    const double *Md;     // [dim][dim] M in binary64 (elite re-score)
+    const double *o64;    // [dim] shift in binary64
+    int32_t Kp, Np;       // K padded to 64, N padded to 128
+    int32_t bf16;         // 1: BF16 estimate + binary32 re-score
+};
+
 // Everything a kernel needs, passed by value.  Element pointers are typed
 // by the handle's precision (float or double).
 struct Params {
@@ -35,6 +53,8 @@ struct Params {
     int32_t Nt, Ks;       // MFMA tiles: output column tiles of 16, k-steps of 4
     int32_t rows;         // ranks per workgroup of the tiled step: 16, or 512 / lanes
     int32_t rank_lds;     // 1: the sort stages the keys in LDS (pop <= 1024)
+    int32_t gemm;         // 1: the GEMM form of the step (gb)
+    GemmBufs gb;
                           // (Ks padded to 32 or a multiple of 8; A and B zero there)
     int32_t trace;        // 1: write candidates to the trace buffers
     uint32_t seed_lo, seed_hi, run;
@@ -75,6 +95,12 @@ hipError_t launch_step(const Params &p, bool fp64, hipStream_t s);
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s);
 hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream_t s);
 hipError_t launch_histogram(const uint8_t *img, uint64_t n, uint32_t *hist, hipStream_t s);
+
+// The GEMM form of one step (or of the initial evaluation), and the binary64
+// re-score of one row x (device, binary64) into out[0].
+hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStream_t s);
+hipError_t launch_elite_f64(const Params &p, const GemmBufs &w, const double *x, double *out,
+                            hipStream_t s);
 
 // Batches: every run of a step launch has the same kernel shape
 // (step_shape), one rank launch per precision.

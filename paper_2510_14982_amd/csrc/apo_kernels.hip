@@ -362,6 +362,7 @@ hipError_t launch_tile_batch_f32(const Params &proto, const BatchLaunch &b, hipS
 hipError_t launch_tile_batch_f64(const Params &proto, const BatchLaunch &b, hipStream_t s);
 
 static hipError_t launch_step_any(const Params &p, bool fp64, int init, hipStream_t s) {
+    if (p.gemm) return launch_gemm_step(p, p.gb, init, s);
     const bool tile = p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
     if (tile) return fp64 ? launch_tile_f64(p, init, s) : launch_tile_f32(p, init, s);
     return fp64 ? launch_elem_f64(p, init, s) : launch_elem_f32(p, init, s);

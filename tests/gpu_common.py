@@ -40,7 +40,7 @@ def need_gpu():
 def make_pair(apo, *, dim, pop, kind="rastrigin", precision="fp64", rotated=False, np_pairs=1,
               pf_max=0.1, seed=1, max_iter=100, lb=-100.0, ub=100.0, shift=True, hist=None,
               trace=True, run_id=0, pdr_plus=False):
-    dt = np.float32 if precision == "fp32" else np.float64
+    dt = np.float32 if precision in ("fp32", "bf16") else np.float64
     lbv = np.broadcast_to(np.asarray(lb, np.float64), (dim,)).astype(dt).astype(np.float64)
     ubv = np.broadcast_to(np.asarray(ub, np.float64), (dim,)).astype(dt).astype(np.float64)
     o = None

@@ -97,6 +97,14 @@ def test_create_rejects_bad_arguments_on_the_host(L):
     assert _create(L, pop=65537) == UNSUP
     assert _create(L, dim=2000, lb=np.zeros(2000), ub=np.ones(2000)) == UNSUP
     assert _create(L, dim=600, lb=np.zeros(600), ub=np.ones(600), rot=np.eye(600)) == UNSUP
+    # BF16 is for rotated objectives; the GEMM form takes separable ones
+    assert _create(L, precision=2) == INVAL
+    assert _create(L, dim=600, lb=np.zeros(600), ub=np.ones(600), rot=np.eye(600), precision=1,
+                   kind=2) == UNSUP
+    assert _create(L, dim=8, lb=np.zeros(8), ub=np.ones(8), rot=np.eye(8), precision=2,
+                   kind=2) == UNSUP
+    assert _create(L, dim=1100, lb=np.zeros(1100), ub=np.ones(1100), rot=np.eye(1100),
+                   precision=1) == UNSUP
 
 
 def test_null_handles_and_histogram_arguments(L):
