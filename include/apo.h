@@ -175,6 +175,20 @@ int apo_time_kernels(apo_t *h, int32_t n, double *avg_us);
  * n < 2^32.  Asynchronous.  APO_E_INVAL for NULL pointers. */
 int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint32_t *d_hist, void *stream);
 
+/* Stage times of a handle whose step runs in the GEMM form (rotated
+ * objectives above 512 dimensions in binary32, and every APO_BF16 handle):
+ * n more iterations (clipped like apo_run), HIP events on the handle's
+ * stream around each launch, average microseconds per iteration into
+ * us[6]: [0] candidates, [1] product (BF16 estimate, or binary32), [2] BF16
+ * classification, [3] binary32 re-score product, [4] selection, [5] sort
+ * ([2] and [3] are ~0 in binary32).  Returns n, or APO_E_STATE for a handle
+ * of another form. */
+int apo_time_gemm_stages(apo_t *h, int32_t iters, double *us);
+
+/* BF16 form: candidates re-scored in binary32 so far and candidates whose
+ * fitness was estimated (pop per iteration); both 0 for other handles. */
+int apo_precision_stats(apo_t *h, int64_t *rescored, int64_t *estimated);
+
 /* Static description of a status code. */
 const char *apo_strerror(int status);
 

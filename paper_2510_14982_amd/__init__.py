@@ -143,6 +143,21 @@ class APO:
         n = _check(lib().apo_time_kernels(self._h, int(iters), _dptr(out)), "apo_time_kernels")
         return n, {"rank_us": float(out[0]), "step_us": float(out[1])}
 
+    def time_gemm_stages(self, iters: int):
+        """Per-stage microseconds per iteration of the GEMM form."""
+        out = np.zeros(6)
+        n = _check(lib().apo_time_gemm_stages(self._h, int(iters), _dptr(out)),
+                   "apo_time_gemm_stages")
+        names = ("candidates", "product", "classify", "rescore_product", "select", "sort")
+        return n, dict(zip(names, map(float, out)))
+
+    def precision_stats(self):
+        """(candidates re-scored in binary32, candidates estimated) of the
+        BF16 form."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().apo_precision_stats(self._h, C.byref(a), C.byref(b)), "apo_precision_stats")
+        return a.value, b.value
+
     # -- results --------------------------------------------------------
     def best(self):
         x = np.zeros(self.dim)

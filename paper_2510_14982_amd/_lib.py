@@ -105,6 +105,10 @@ def lib():
     L.apo_batch_tune.argtypes = [vp, i32, P(i32), P(d)]
     L.apo_batch_destroy.restype = C.c_int
     L.apo_batch_destroy.argtypes = [vp]
+    L.apo_time_gemm_stages.restype = C.c_int
+    L.apo_time_gemm_stages.argtypes = [vp, i32, P(d)]
+    L.apo_precision_stats.restype = C.c_int
+    L.apo_precision_stats.argtypes = [vp, P(C.c_int64), P(C.c_int64)]
     L.apo_strerror.restype = C.c_char_p
     L.apo_strerror.argtypes = [C.c_int]
     _lib = L

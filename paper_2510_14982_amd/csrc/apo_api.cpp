@@ -25,7 +25,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Offsets of every device array inside the workspace (bytes, 256-aligned).
 struct Layout {
-    size_t gYr, gAb, gan, gP1, gP2, glist, gcount, gMb, gMf, gMd, go64;   // GEMM form
+    size_t gYr, gAb, gan, gP1, gP2, glist, gstat, gcount, gtot, gMb, gMf, gMd, go64;   // GEMM form
     int Kp, Np;
     size_t X[2], F, perm, Fs, drf, ctrl, p_ah, fscale, cnear, p_dr, lb, ub, shift, rotp, htab, hist,
         best, trY, trF, trOp, total;
@@ -72,7 +72,7 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     const bool gf = gemm_form(dim, o);
     L.rotp = (o.objective.rot && !gf) ? take((size_t)L.Ks * L.Nt * 64 * es) : 0;
     if (gf) {
-        L.Kp = (dim + 63) / 64 * 64;
+        L.Kp = (dim + 127) / 128 * 128;   // whole product chunks of 256 bytes (BF16)
         L.Np = (dim + 127) / 128 * 128;
         const bool bf = o.precision == APO_BF16;
         L.gYr = take((size_t)pop * L.Dp * 4);
@@ -81,7 +81,9 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
         L.gP1 = take((size_t)pop * (L.Np / 64) * 4);
         L.gP2 = take((size_t)pop * (L.Np / 64) * 4);
         L.glist = take((size_t)pop * 4);
+        L.gstat = take((size_t)pop * 4);
         L.gcount = take(4);
+        L.gtot = take(8);
         L.gMb = bf ? take((size_t)L.Np * L.Kp * 2) : 0;
         L.gMf = take((size_t)L.Np * L.Kp * 4);
         L.gMd = take((size_t)dim * dim * 8);
@@ -572,7 +574,9 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         g.P1 = (float *)(ws + L.gP1);
         g.P2 = (float *)(ws + L.gP2);
         g.list = (int32_t *)(ws + L.glist);
+        g.status = (int32_t *)(ws + L.gstat);
         g.count = (int32_t *)(ws + L.gcount);
+        g.total = (unsigned long long *)(ws + L.gtot);
         g.Mb = L.gMb ? (const uint16_t *)(ws + L.gMb) : nullptr;
         g.Mf = (const float *)(ws + L.gMf);
         g.Md = (const double *)(ws + L.gMd);
@@ -811,6 +815,61 @@ int apo_time_kernels(apo_t *h, int32_t iters, double *avg_us) {
     avg_us[0] = 1000.0 * sum_rank / n;
     avg_us[1] = 1000.0 * sum_step / n;
     return n;
+}
+
+int apo_time_gemm_stages(apo_t *h, int32_t iters, double *us) {
+    if (!h || iters < 1 || !us) return APO_E_INVAL;
+    if (h->batch_view || !h->p.gemm) return APO_E_STATE;
+    if (h->poisoned) return APO_E_DEVICE;
+    int32_t n = h->T - h->t;
+    if (iters < n) n = iters;
+    if (n <= 0) return APO_E_DONE;
+    hipEvent_t ev[7];
+    for (int i = 0; i < 7; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+            return APO_E_DEVICE;
+        }
+    double sum[6] = {0, 0, 0, 0, 0, 0};
+    int rc = APO_OK;
+    for (int32_t it = 0; it < n && rc == APO_OK; ++it) {
+        bool ok = hipEventRecord(ev[0], h->stream) == hipSuccess &&
+                  apok::launch_rank(h->p, h->fp64, h->stream) == hipSuccess &&
+                  hipEventRecord(ev[1], h->stream) == hipSuccess;
+        for (int st = 0; ok && st < 5; ++st)
+            ok = apok::launch_gemm_stage(h->p, h->p.gb, 0, st, h->stream) == hipSuccess &&
+                 hipEventRecord(ev[2 + st], h->stream) == hipSuccess;
+        ok = ok && hipEventSynchronize(ev[6]) == hipSuccess;
+        float ms = 0.f;
+        for (int st = 0; ok && st < 6; ++st) {
+            ok = hipEventElapsedTime(&ms, ev[st], ev[st + 1]) == hipSuccess;
+            sum[st == 0 ? 5 : st - 1] += 1000.0 * ms;
+        }
+        if (!ok) {
+            h->poisoned = true;
+            rc = APO_E_DEVICE;
+        } else {
+            ++h->t;
+        }
+    }
+    for (int i = 0; i < 7; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc != APO_OK) return rc;
+    for (int i = 0; i < 6; ++i) us[i] = sum[i] / n;
+    return n;
+}
+
+int apo_precision_stats(apo_t *h, int64_t *rescored, int64_t *estimated) {
+    if (!h || !rescored || !estimated) return APO_E_INVAL;
+    if (h->poisoned) return APO_E_DEVICE;
+    *rescored = 0;
+    *estimated = 0;
+    if (!h->p.gemm || !h->p.gb.bf16) return APO_OK;
+    unsigned long long tot = 0;
+    APO_HIP(h, hipMemcpyAsync(&tot, h->p.gb.total, 8, hipMemcpyDeviceToHost, h->stream));
+    APO_HIP(h, hipStreamSynchronize(h->stream));
+    *rescored = (int64_t)tot;
+    *estimated = (int64_t)h->pop * (int64_t)h->t;
+    return APO_OK;
 }
 
 int apo_info(const apo_t *h, int32_t *iter, int64_t *fes) {

@@ -15,8 +15,11 @@
 namespace apok {
 
 constexpr int kGM = 128, kGN = 128;      // output tile of a workgroup
-constexpr int kGRowB = 128;              // bytes of K per row and chunk
-constexpr int kGLds = kGRowB + 16;       // LDS row stride in bytes
+constexpr int kGRowB = 256;              // bytes of K per row and chunk
+constexpr int kGLds = kGRowB + 16;       // LDS row stride in bytes (17 x 16: rows of a
+                                         // fragment read fall in distinct bank groups)
+constexpr int kGQ = kGRowB / 32;         // 16-byte vectors per loader thread and matrix
+constexpr size_t kGemmLds = 2 * (size_t)kGM * kGLds;   // dynamic LDS of the product
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
@@ -97,10 +100,11 @@ __global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init)
     if (p.trace && !init && lane == 0) p.trOp[c.id] = c.op;
 }
 
-// One chunk (128 bytes of K) of a loader thread's A and B rows into
-// registers: B from the packed M rows; A either stored (BF16) or y - o.
+// One chunk (kGRowB bytes of K) of a loader thread's half rows of A and B
+// into registers: B from the packed M rows; A either stored (BF16) or
+// y - o computed from the binary32 candidates.
 struct GemmChunk {
-    uint4 a0, a1, a2, a3, b0, b1, b2, b3;
+    uint4 a[kGQ], b[kGQ];
 };
 
 template <typename TA>
@@ -108,47 +112,43 @@ __device__ __forceinline__ GemmChunk gemm_fetch(const GemmRun &g, const unsigned
                                                 int arow, bool live, int lh, int kc) {
     constexpr int ES = sizeof(TA);
     GemmChunk c;
-    uint4 ra[4];
     const uint4 *bp = (const uint4 *)(Bp + (size_t)kc * ES);
-    c.b0 = bp[0];
-    c.b1 = bp[1];
-    c.b2 = bp[2];
-    c.b3 = bp[3];
-    if (ES == 2) {
-        const uint4 *ap =
-            (const uint4 *)((const unsigned char *)g.Ab + ((size_t)arow * g.Kp + kc) * 2 + lh * 64);
-        const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ra[q] = live ? ap[q] : zero4;
+    for (int q = 0; q < kGQ; ++q) c.b[q] = bp[q];
+    if constexpr (ES == 2) {
+        const uint4 *ap = (const uint4 *)((const unsigned char *)g.Ab +
+                                          ((size_t)arow * g.Kp + kc) * 2 + lh * (kGRowB / 2));
+        // a row past the list end reads row 0 (arow) and is zeroed here
+#pragma unroll
+        for (int q = 0; q < kGQ; ++q) {
+            const uint4 v = ap[q];
+            c.a[q] = live ? v : make_uint4(0u, 0u, 0u, 0u);
+        }
     } else {
-        const int k0 = kc + lh * 16;
+        const int k0 = kc + lh * (kGRowB / 8);   // 4-byte elements of the half row
         const float *yr = g.Yr + (size_t)arow * g.Dp;
-        if (live && k0 + 16 <= g.D) {
+        if (live && k0 + 4 * kGQ <= g.D) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < kGQ; ++q) {
                 const float4 y4 = ((const float4 *)(yr + k0))[q];
                 const float4 o4 = ((const float4 *)(g.o + k0))[q];
-                ra[q] = make_uint4(__float_as_uint(y4.x - o4.x), __float_as_uint(y4.y - o4.y),
-                                   __float_as_uint(y4.z - o4.z), __float_as_uint(y4.w - o4.w));
+                c.a[q] = make_uint4(__float_as_uint(y4.x - o4.x), __float_as_uint(y4.y - o4.y),
+                                    __float_as_uint(y4.z - o4.z), __float_as_uint(y4.w - o4.w));
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < kGQ; ++q) {
                 float v[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int k = k0 + 4 * q + e;
                     v[e] = (live && k < g.D) ? yr[k] - g.o[k] : 0.f;
                 }
-                ra[q] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]),
-                                   __float_as_uint(v[2]), __float_as_uint(v[3]));
+                c.a[q] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]),
+                                    __float_as_uint(v[2]), __float_as_uint(v[3]));
             }
         }
     }
-    c.a0 = ra[0];
-    c.a1 = ra[1];
-    c.a2 = ra[2];
-    c.a3 = ra[3];
     return c;
 }
 
@@ -158,24 +158,25 @@ __device__ __forceinline__ GemmChunk gemm_fetch(const GemmRun &g, const unsigned
 // Ackley, sum z^2 otherwise).  Rows are list slots (the ranks of a rescore
 // list) or ranks.  TA = uint16_t (BF16 bits, A read from Ab) or float (A =
 // y - o computed from Yr while loading).  Workgroup: 4 wavefronts, each a
-// 64 x 64 quadrant of 4 x 4 MFMA 16 x 16 tiles; K in chunks of 128 bytes
+// 64 x 64 quadrant of 4 x 4 MFMA 16 x 16 tiles; K in chunks of 256 bytes
 // per row, the next chunk fetched into registers during the MFMA work.
 // ---------------------------------------------------------------------------
 template <typename TA>
 __global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
     constexpr int ES = sizeof(TA), KC = kGRowB / ES, KSUB = ES == 2 ? 16 : 4;
-    __shared__ __align__(16) unsigned char sA[kGM * kGLds];
-    __shared__ __align__(16) unsigned char sB[kGN * kGLds];
+    extern __shared__ __align__(16) unsigned char gsm[];
+    unsigned char *sA = gsm, *sB = gsm + kGM * kGLds;
     const int nrows = g.list ? *g.count : g.rows;
     const int m0 = blockIdx.y * kGM;
     if (m0 >= nrows) return;   // the whole workgroup: no barrier is skipped
     const int n0 = blockIdx.x * kGN;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
-    const int lr = tid >> 1, lh = tid & 1;                  // loader: row, 64-byte half
+    const int lr = tid >> 1, lh = tid & 1;                  // loader: row, half chunk
     const int slot = m0 + lr;
     const bool live = slot < nrows;
     const int arow = live ? (g.list ? g.list[slot] : slot) : 0;
-    const unsigned char *Bp = (const unsigned char *)g.B + (size_t)(n0 + lr) * g.Kp * ES + lh * 64;
+    const unsigned char *Bp =
+        (const unsigned char *)g.B + (size_t)(n0 + lr) * g.Kp * ES + lh * (kGRowB / 2);
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -185,15 +186,19 @@ __global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
     GemmChunk ch = gemm_fetch<TA>(g, Bp, arow, live, lh, 0);
     for (int kc = 0; kc < g.Kp; kc += KC) {
         __syncthreads();   // the previous chunk's readers are done
-        uint4 *da = (uint4 *)(sA + lr * kGLds + lh * 64), *db = (uint4 *)(sB + lr * kGLds + lh * 64);
-        da[0] = ch.a0; da[1] = ch.a1; da[2] = ch.a2; da[3] = ch.a3;
-        db[0] = ch.b0; db[1] = ch.b1; db[2] = ch.b2; db[3] = ch.b3;
+        uint4 *da = (uint4 *)(sA + lr * kGLds + lh * (kGRowB / 2));
+        uint4 *db = (uint4 *)(sB + lr * kGLds + lh * (kGRowB / 2));
+#pragma unroll
+        for (int q = 0; q < kGQ; ++q) {
+            da[q] = ch.a[q];
+            db[q] = ch.b[q];
+        }
         __syncthreads();
         if (kc + KC < g.Kp)   // in flight during the MFMA work
             ch = gemm_fetch<TA>(g, Bp, arow, live, lh, kc + KC);
 #pragma unroll
         for (int ks = 0; ks < KC / KSUB; ++ks) {
-            if (ES == 2) {
+            if constexpr (ES == 2) {
                 // 16 x 16 x 16 BF16: lane l holds A[l % 16][4 (l / 16) .. + 3]
                 // and B[4 (l / 16) .. + 3][l % 16]
                 const int kb = (ks * 16 + 4 * (l >> 4)) * 2;
@@ -292,23 +297,34 @@ __device__ __forceinline__ void copy_row(float *dst, const float *src, int D, in
     }
 }
 
-// Binary32 selection (one wavefront per slot): rows of the list, or every
-// rank.  Writes the chosen row and fitness of the next buffer.
-__global__ __launch_bounds__(256) void gemm_select(Params p, GemmRun g, GemmBufs w, int init) {
+// Selection (one wavefront per rank).  mode 0: every rank's binary32
+// fitness from the product's partials (slot = rank); mode 1 (BF16 form):
+// ranks the classification settled as rejections carry the parent row over,
+// the others take their binary32 fitness from the re-score product (slot =
+// status[r]).  Writes the chosen row and fitness of the next buffer.
+__global__ __launch_bounds__(256) void gemm_select(Params p, GemmRun g, GemmBufs w, int init,
+                                                   int mode) {
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int t = init ? 0 : __hip_atomic_load(&p.ctrl->t_next, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
-    if (!init && blockIdx.x == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
-    const int nrows = g.list ? *g.count : p.pop;
-    const int slot = blockIdx.x * 4 + wave;
-    if (slot >= nrows) return;
-    const int r = g.list ? g.list[slot] : slot;
+    if (!init && blockIdx.x == 0 && threadIdx.x == 0) {
+        p.ctrl->t = t;   // iteration closed
+        if (mode == 1) *w.total += (unsigned long long)*w.count;
+    }
+    const int r = blockIdx.x * 4 + wave;
+    if (r >= p.pop) return;
     const int id = init ? r : p.perm[r];
-    float s1, s2;
-    row_sums(g, slot, s1, s2);
-    const float fnew = row_objective(p.kind, p.dim, s1, s2);
+    const int slot = mode == 1 ? w.status[r] : r;
     const float fold = init ? 0.f : ((const float *)p.Fs)[r];
-    const bool accept = init || fnew < fold;
+    float fnew;
+    if (slot >= 0) {
+        float s1, s2;
+        row_sums(g, slot, s1, s2);
+        fnew = row_objective(p.kind, p.dim, s1, s2);
+    } else {
+        fnew = w.anorm[r];   // the classification left the BF16 estimate here
+    }
+    const bool accept = init || (slot >= 0 && fnew < fold);
     const float *X0 = (const float *)p.X[(t + 1) & 1];
     float *X1 = (float *)p.X[t & 1];
     const float *y = w.Yr + (size_t)r * p.Dp;
@@ -320,51 +336,56 @@ __global__ __launch_bounds__(256) void gemm_select(Params p, GemmRun g, GemmBufs
     }
 }
 
-// BF16 pass (one wavefront per rank): from the estimate F^ and the bound B
-// on |F^ - F32| (F32 = the binary32 form's value of the same candidate),
-// a candidate with F^ - B >= F_old is certainly rejected (the parent row is
-// carried over); every other candidate goes to the rescore list.
+// BF16 classification (one thread per rank): from the estimate F^ and the
+// bound B on |F^ - F32| (F32 = the binary32 form's value of the same
+// candidate), a candidate with F^ - B >= F_old is certainly rejected
+// (status -1); every other rank is appended to the re-score list (status =
+// its slot), with one atomic per workgroup.  The estimate is left in
+// anorm[r] for the trace.
 __global__ __launch_bounds__(256) void gemm_classify(Params p, GemmRun g, GemmBufs w) {
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int r = blockIdx.x * 4 + wave;
-    if (r >= p.pop) return;
-    const int t = __hip_atomic_load(&p.ctrl->t_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int id = p.perm[r];
+    __shared__ int s_n[4], s_base;
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+    const int r = blockIdx.x * 256 + tid;
     const int D = p.dim;
-    float s1, s2;
-    row_sums(g, r, s1, s2);
-    const float fhat = row_objective(p.kind, D, s1, s2);
-    const float fold = ((const float *)p.Fs)[r];
-    // Coordinate error: BF16 operands (unit roundoff 2^-8 each) and two
-    // binary32 accumulations over D terms, times sum_j |M_ij| |a_j| <=
-    // ||a||_2 (orthogonal rows; the BF16 rows' norms stay within 1.01).
-    const float e = (1.01f * 0.0078125f + 2.f * (float)(D + 2) * 5.9604645e-8f) * 1.01f *
-                    w.anorm[r];
-    const float ce = fminf(2.f, 6.2831853f * e);        // |cos 2 pi a - cos 2 pi b| bound
-    const float gD = 2.f * (float)D * 5.9604645e-8f;     // binary32 evaluation of the sums
-    float B;
-    if (p.kind == K_ACKLEY) {
-        const float rr = sqrtf(s1 / (float)D);
-        B = 4.f * e + 2.7182818f * ce + gD * (4.f * rr + 2.7182818f) ;
-    } else {
-        const float zn = sqrtf(s2);                     // ||z^||_2
-        B = 2.f * e * sqrtf((float)D) * zn + (float)D * e * e +
-            (p.kind == K_RASTRIGIN ? 10.f * (float)D * ce : 0.f) +
-            gD * (s2 + (p.kind == K_RASTRIGIN ? 20.f * (float)D : 0.f));
-    }
-    B = B * 1.05f + 1e-6f * (fabsf(fhat) + fabsf(fold));
-    if (fhat - B >= fold) {
-        const float *X0 = (const float *)p.X[(t + 1) & 1];
-        float *X1 = (float *)p.X[t & 1];
-        copy_row(X1 + (size_t)id * p.Dp, X0 + (size_t)id * p.Dp, D, l);
-        if (l == 0) ((float *)p.F)[id] = fold;
-        if (p.trace) {
-            copy_row((float *)p.trY + (size_t)id * p.Dp, w.Yr + (size_t)r * p.Dp, D, l);
-            if (l == 0) ((float *)p.trF)[id] = fhat;
+    bool need = false;
+    float fhat = 0.f;
+    if (r < p.pop) {
+        float s1, s2;
+        row_sums(g, r, s1, s2);
+        fhat = row_objective(p.kind, D, s1, s2);
+        const float fold = ((const float *)p.Fs)[r];
+        // Coordinate error: BF16 operands (unit roundoff 2^-8 each) and two
+        // binary32 accumulations over D terms, times sum_j |M_ij| |a_j| <=
+        // ||a||_2 (orthogonal rows; the BF16 rows' norms stay within 1.01).
+        const float e = (1.01f * 0.0078125f + 2.f * (float)(D + 2) * 5.9604645e-8f) * 1.01f *
+                        w.anorm[r];
+        const float ce = fminf(2.f, 6.2831853f * e);        // |cos 2 pi a - cos 2 pi b|
+        const float gD = 2.f * (float)D * 5.9604645e-8f;     // binary32 evaluation of sums
+        float B;
+        if (p.kind == K_ACKLEY) {
+            const float rr = sqrtf(s1 / (float)D);
+            B = 4.f * e + 2.7182818f * ce + gD * (4.f * rr + 2.7182818f);
+        } else {
+            const float zn = sqrtf(s2);                      // ||z^||_2
+            B = 2.f * e * sqrtf((float)D) * zn + (float)D * e * e +
+                (p.kind == K_RASTRIGIN ? 10.f * (float)D * ce : 0.f) +
+                gD * (s2 + (p.kind == K_RASTRIGIN ? 20.f * (float)D : 0.f));
         }
-    } else if (l == 0) {
-        const int k = atomicAdd(w.count, 1);
-        w.list[k] = r;
+        B = B * 1.05f + 1e-6f * (fabsf(fhat) + fabsf(fold));
+        need = !(fhat - B >= fold);
+    }
+    const uint64_t bal = __ballot(need);
+    const int before = (int)__popcll(bal & ((1ull << l) - 1ull));
+    if (l == 0) s_n[wave] = (int)__popcll(bal);
+    __syncthreads();
+    if (tid == 0) s_base = atomicAdd(w.count, s_n[0] + s_n[1] + s_n[2] + s_n[3]);
+    __syncthreads();
+    int off = s_base + before;
+    for (int q = 0; q < wave; ++q) off += s_n[q];
+    if (r < p.pop) {
+        w.status[r] = need ? off : -1;
+        if (need) w.list[off] = r;
+        w.anorm[r] = fhat;
     }
 }
 
@@ -447,32 +468,49 @@ static hipError_t launch_cand(const Params &p, const GemmBufs &w, int init, hipS
 
 static hipError_t launch_gemm(const GemmRun &g, bool bf16, hipStream_t s) {
     const dim3 grid((unsigned)(g.Np / kGN), (unsigned)((g.rows + kGM - 1) / kGM)), block(256);
+    const void *fn = bf16 ? (const void *)gemm_obj<uint16_t> : (const void *)gemm_obj<float>;
+    const hipError_t ea =
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
+    if (ea != hipSuccess) return ea;
     if (bf16)
-        hipLaunchKernelGGL(gemm_obj<uint16_t>, grid, block, 0, s, g);
+        hipLaunchKernelGGL(gemm_obj<uint16_t>, grid, block, kGemmLds, s, g);
     else
-        hipLaunchKernelGGL(gemm_obj<float>, grid, block, 0, s, g);
+        hipLaunchKernelGGL(gemm_obj<float>, grid, block, kGemmLds, s, g);
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStream_t s) {
+hipError_t launch_gemm_stage(const Params &p, const GemmBufs &w, int init, int stage,
+                             hipStream_t s) {
     const bool bf16 = w.bf16 && !init;   // the initial fitness is taken in binary32
     const dim3 sgrid((unsigned)((p.pop + 3) / 4)), sblock(256);
-    hipError_t e = bf16 ? launch_cand<true>(p, w, init, s) : launch_cand<false>(p, w, init, s);
-    if (e != hipSuccess) return e;
-    if (!bf16) {
-        const GemmRun g = gemm_run(p, w, false, false);
-        if ((e = launch_gemm(g, false, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(gemm_select, sgrid, sblock, 0, s, p, g, w, init);
+    switch (stage) {
+    case 0:
+        return bf16 ? launch_cand<true>(p, w, init, s) : launch_cand<false>(p, w, init, s);
+    case 1:
+        return launch_gemm(gemm_run(p, w, bf16, false), bf16, s);
+    case 2:
+        if (!bf16) return hipSuccess;
+        hipLaunchKernelGGL(gemm_classify, dim3((unsigned)((p.pop + 255) / 256)), sblock, 0, s, p,
+                           gemm_run(p, w, true, false), w);
         return hipGetLastError();
+    case 3:
+        if (!bf16) return hipSuccess;
+        return launch_gemm(gemm_run(p, w, false, true), false, s);
+    case 4:
+        hipLaunchKernelGGL(gemm_select, sgrid, sblock, 0, s, p, gemm_run(p, w, false, false), w,
+                           init, bf16 ? 1 : 0);
+        return hipGetLastError();
+    default:
+        return hipErrorInvalidValue;
     }
-    const GemmRun gb = gemm_run(p, w, true, false);
-    if ((e = launch_gemm(gb, true, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(gemm_classify, sgrid, sblock, 0, s, p, gb, w);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const GemmRun gf = gemm_run(p, w, false, true);
-    if ((e = launch_gemm(gf, false, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(gemm_select, sgrid, sblock, 0, s, p, gf, w, 0);
-    return hipGetLastError();
+}
+
+hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStream_t s) {
+    for (int stage = 0; stage < 5; ++stage) {
+        const hipError_t e = launch_gemm_stage(p, w, init, stage, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_elite_f64(const Params &p, const GemmBufs &w, const double *x, double *out,

@@ -34,12 +34,14 @@ struct GemmBufs {
     float *anorm;         // [pop] ||y - o||_2 (BF16 form)
     float *P1, *P2;       // [pop][Np / 64] partial row sums
     int32_t *list;        // [pop] ranks to re-score in binary32
+    int32_t *status;      // [pop] rank's slot in the list, or -1 (settled rejection)
     int32_t *count;       // its length
+    unsigned long long *total;   // rows re-scored so far (BF16 form)
     const uint16_t *Mb;   // [Np][Kp] M in BF16
     const float *Mf;      // [Np][Kp] M in binary32
     const double *Md;     // [dim][dim] M in binary64 (elite re-score)
     const double *o64;    // [dim] shift in binary64
-    int32_t Kp, Np;       // K padded to 64, N padded to 128
+    int32_t Kp, Np;       // K and N padded to 128
     int32_t bf16;         // 1: BF16 estimate + binary32 re-score
 };
 
@@ -99,6 +101,10 @@ hipError_t launch_histogram(const uint8_t *img, uint64_t n, uint32_t *hist, hipS
 // The GEMM form of one step (or of the initial evaluation), and the binary64
 // re-score of one row x (device, binary64) into out[0].
 hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStream_t s);
+// One stage of it: 0 candidates, 1 product (BF16 estimate or binary32),
+// 2 BF16 classification, 3 binary32 re-score product, 4 selection.
+hipError_t launch_gemm_stage(const Params &p, const GemmBufs &w, int init, int stage,
+                             hipStream_t s);
 hipError_t launch_elite_f64(const Params &p, const GemmBufs &w, const double *x, double *out,
                             hipStream_t s);
 
