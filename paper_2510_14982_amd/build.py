@@ -17,6 +17,11 @@ LIB = os.path.join(HERE, "libapo.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["apo_kernels.hip", "apo_step_elem_f32.hip", "apo_step_elem_f64.hip",
            "apo_step_tile_f32.hip", "apo_step_tile_f64.hip", "apo_gemm.hip", "apo_api.cpp"]
+# Per-source options.  The product kernels of the GEMM form keep their MFMA
+# accumulators in the architectural VGPRs (the instructions' VGPR form):
+# without it the register allocator splits the loop-carried accumulators
+# between the two register files and copies them every K chunk.
+EXTRA = {"apo_gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def hipcc() -> str:
@@ -39,7 +44,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [cc] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc] + flags() + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".hip"):
             cmd[1:1] = ["-x", "hip"]
         if verbose:

@@ -1,7 +1,7 @@
 // apo_gemm.hip -- the GEMM form of the step for rotated objectives of large
 // dimension (binary32 state): per iteration
 //   candidates  -> Yr [ps][Dp] (rank order) and A = bf16(y - o) [ps][Kp]
-//   Z = A M^T on the matrix cores, 128 x 128 output tiles, with the
+//   Z = A M^T on the matrix cores (binary32 or BF16 operands), with the
 //                  objective's row sums fused into the epilogue (partials)
 //   selection   -> strict greedy choice, rows written to the next buffer.
 // With bfloat16 (BF16) operands the product is a cheap estimate: each
@@ -14,14 +14,31 @@
 
 namespace apok {
 
+// Binary32 product: 128 x 128 output tile per workgroup, both operands staged
+// through LDS in chunks of 32 K.
 constexpr int kGM = 128, kGN = 128;      // output tile of a workgroup
-constexpr int kGRowB = 256;              // bytes of K per row and chunk
-constexpr int kGLds = kGRowB + 16;       // LDS row stride in bytes (17 x 16: rows of a
+constexpr int kGRowB = 128;              // bytes of K per row and chunk
+constexpr int kGLds = kGRowB + 16;       // LDS row stride in bytes (9 x 16: rows of a
                                          // fragment read fall in distinct bank groups)
 constexpr int kGQ = kGRowB / 32;         // 16-byte vectors per loader thread and matrix
 constexpr size_t kGemmLds = 2 * (size_t)kGM * kGLds;   // dynamic LDS of the product
 
-typedef short s16x4 __attribute__((ext_vector_type(4)));
+// BF16 product: 256 x 128 output tile per workgroup (4 wavefronts of 64 rows),
+// A straight from global memory into fragments, M's 128 rows through LDS in
+// chunks of kBK K, two buffers.
+constexpr int kBM = 256, kBN = 128, kBK = 32;
+constexpr int kBKS = kBK / 32;           // MFMA k-steps per chunk
+constexpr int kBU = kBK / 8;             // 16-byte units per row and chunk
+constexpr int kBQ = kBN * kBU / 256;     // units each thread stages per chunk
+constexpr int kBLds = 2 * kBK + 16;      // LDS row stride in bytes (odd number of units)
+constexpr size_t kBLdsBytes = 2 * (size_t)kBN * kBLds;
+// LDS reserved at launch: more than half of a CU's 160 KB, so that a CU
+// holds one workgroup and a grid of one workgroup per CU spreads over all CUs.
+constexpr size_t kBLdsLaunch = 96 * 1024;
+static_assert(kBLdsBytes <= kBLdsLaunch, "BF16 product LDS");
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // One product launch: rows are list slots (list != nullptr: slot k is rank
 // list[k], *count slots) or ranks (rows of them).
@@ -101,69 +118,73 @@ __global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init)
 }
 
 // One chunk (kGRowB bytes of K) of a loader thread's half rows of A and B
-// into registers: B from the packed M rows; A either stored (BF16) or
-// y - o computed from the binary32 candidates.
+// into registers: B from the packed binary32 M rows, A = y - o computed from
+// the binary32 candidates.
 struct GemmChunk {
     uint4 a[kGQ], b[kGQ];
 };
 
-template <typename TA>
 __device__ __forceinline__ GemmChunk gemm_fetch(const GemmRun &g, const unsigned char *Bp,
                                                 int arow, bool live, int lh, int kc) {
-    constexpr int ES = sizeof(TA);
     GemmChunk c;
-    const uint4 *bp = (const uint4 *)(Bp + (size_t)kc * ES);
+    const uint4 *bp = (const uint4 *)(Bp + (size_t)kc * 4);
 #pragma unroll
     for (int q = 0; q < kGQ; ++q) c.b[q] = bp[q];
-    if constexpr (ES == 2) {
-        const uint4 *ap = (const uint4 *)((const unsigned char *)g.Ab +
-                                          ((size_t)arow * g.Kp + kc) * 2 + lh * (kGRowB / 2));
-        // a row past the list end reads row 0 (arow) and is zeroed here
+    const int k0 = kc + lh * (kGRowB / 8);   // 4-byte elements of the half row
+    const float *yr = g.Yr + (size_t)arow * g.Dp;
+    if (live && k0 + 4 * kGQ <= g.D) {
 #pragma unroll
         for (int q = 0; q < kGQ; ++q) {
-            const uint4 v = ap[q];
-            c.a[q] = live ? v : make_uint4(0u, 0u, 0u, 0u);
+            const float4 y4 = ((const float4 *)(yr + k0))[q];
+            const float4 o4 = ((const float4 *)(g.o + k0))[q];
+            c.a[q] = make_uint4(__float_as_uint(y4.x - o4.x), __float_as_uint(y4.y - o4.y),
+                                __float_as_uint(y4.z - o4.z), __float_as_uint(y4.w - o4.w));
         }
     } else {
-        const int k0 = kc + lh * (kGRowB / 8);   // 4-byte elements of the half row
-        const float *yr = g.Yr + (size_t)arow * g.Dp;
-        if (live && k0 + 4 * kGQ <= g.D) {
 #pragma unroll
-            for (int q = 0; q < kGQ; ++q) {
-                const float4 y4 = ((const float4 *)(yr + k0))[q];
-                const float4 o4 = ((const float4 *)(g.o + k0))[q];
-                c.a[q] = make_uint4(__float_as_uint(y4.x - o4.x), __float_as_uint(y4.y - o4.y),
-                                    __float_as_uint(y4.z - o4.z), __float_as_uint(y4.w - o4.w));
+        for (int q = 0; q < kGQ; ++q) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + 4 * q + e;
+                v[e] = (live && k < g.D) ? yr[k] - g.o[k] : 0.f;
             }
-        } else {
-#pragma unroll
-            for (int q = 0; q < kGQ; ++q) {
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = k0 + 4 * q + e;
-                    v[e] = (live && k < g.D) ? yr[k] - g.o[k] : 0.f;
-                }
-                c.a[q] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]),
-                                    __float_as_uint(v[2]), __float_as_uint(v[3]));
-            }
+            c.a[q] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]),
+                                __float_as_uint(v[2]), __float_as_uint(v[3]));
         }
     }
     return c;
 }
 
+// Objective terms of one output element, added to the row's two partial sums
+// (P1: the summed terms, or z^2 for Ackley; P2: cos 2 pi z for Ackley, z^2
+// otherwise).  Columns past D (live false) add nothing.
+template <int KIND>
+__device__ __forceinline__ void obj_terms(float z, bool live, float &g1, float &g2) {
+    const float zz = z * z;
+    if constexpr (KIND == K_RASTRIGIN) {
+        g1 += live ? zz - 10.f * cos2pi(z) + 10.f : 0.f;
+        g2 += live ? zz : 0.f;
+    } else if constexpr (KIND == K_ACKLEY) {
+        g1 += live ? zz : 0.f;
+        g2 += live ? cos2pi(z) : 0.f;
+    } else {
+        g1 += live ? zz : 0.f;
+        g2 += live ? zz : 0.f;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Z = A M^T with the objective's per-row sums over each 64-column half tile
-// (P1: the summed terms, or sum z^2 for Ackley; P2: sum cos 2 pi z for
-// Ackley, sum z^2 otherwise).  Rows are list slots (the ranks of a rescore
-// list) or ranks.  TA = uint16_t (BF16 bits, A read from Ab) or float (A =
-// y - o computed from Yr while loading).  Workgroup: 4 wavefronts, each a
-// 64 x 64 quadrant of 4 x 4 MFMA 16 x 16 tiles; K in chunks of 256 bytes
-// per row, the next chunk fetched into registers during the MFMA work.
+// Binary32 product Z = A M^T with the objective's per-row sums over each
+// 64-column half tile fused into the epilogue.  Rows are list slots (the
+// ranks of a re-score list) or ranks; A = y - o is computed from Yr while
+// loading.  Workgroup: 4 wavefronts, each a 64 x 64 quadrant of 4 x 4 MFMA
+// 16 x 16 x 4 tiles; K in chunks of 128 bytes per row, the next chunk
+// fetched into registers during the MFMA work.
 // ---------------------------------------------------------------------------
-template <typename TA>
-__global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
-    constexpr int ES = sizeof(TA), KC = kGRowB / ES, KSUB = ES == 2 ? 16 : 4;
+template <int KIND>
+__global__ __launch_bounds__(256) void gemm_obj_f32(GemmRun g) {
+    constexpr int KC = kGRowB / 4;
     extern __shared__ __align__(16) unsigned char gsm[];
     unsigned char *sA = gsm, *sB = gsm + kGM * kGLds;
     const int nrows = g.list ? *g.count : g.rows;
@@ -176,14 +197,14 @@ __global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
     const bool live = slot < nrows;
     const int arow = live ? (g.list ? g.list[slot] : slot) : 0;
     const unsigned char *Bp =
-        (const unsigned char *)g.B + (size_t)(n0 + lr) * g.Kp * ES + lh * (kGRowB / 2);
+        (const unsigned char *)g.B + (size_t)(n0 + lr) * g.Kp * 4 + lh * (kGRowB / 2);
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int wr = 64 * (wave >> 1), wc = 64 * (wave & 1);
-    GemmChunk ch = gemm_fetch<TA>(g, Bp, arow, live, lh, 0);
+    GemmChunk ch = gemm_fetch(g, Bp, arow, live, lh, 0);
     for (int kc = 0; kc < g.Kp; kc += KC) {
         __syncthreads();   // the previous chunk's readers are done
         uint4 *da = (uint4 *)(sA + lr * kGLds + lh * (kGRowB / 2));
@@ -195,41 +216,22 @@ __global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
         }
         __syncthreads();
         if (kc + KC < g.Kp)   // in flight during the MFMA work
-            ch = gemm_fetch<TA>(g, Bp, arow, live, lh, kc + KC);
+            ch = gemm_fetch(g, Bp, arow, live, lh, kc + KC);
 #pragma unroll
-        for (int ks = 0; ks < KC / KSUB; ++ks) {
-            if constexpr (ES == 2) {
-                // 16 x 16 x 16 BF16: lane l holds A[l % 16][4 (l / 16) .. + 3]
-                // and B[4 (l / 16) .. + 3][l % 16]
-                const int kb = (ks * 16 + 4 * (l >> 4)) * 2;
-                s16x4 a[4], b[4];
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            // 16 x 16 x 4 FP32: lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
+            const int kb = (ks * 4 + (l >> 4)) * 4;
+            float a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = *(const s16x4 *)(sA + (wr + 16 * i + (l & 15)) * kGLds + kb);
-                    b[i] = *(const s16x4 *)(sB + (wc + 16 * i + (l & 15)) * kGLds + kb);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j],
-                                                                             0, 0, 0);
-            } else {
-                // 16 x 16 x 4 FP32: lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
-                const int kb = (ks * 4 + (l >> 4)) * 4;
-                float a[4], b[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = *(const float *)(sA + (wr + 16 * i + (l & 15)) * kGLds + kb);
-                    b[i] = *(const float *)(sB + (wc + 16 * i + (l & 15)) * kGLds + kb);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0,
-                                                                        0, 0);
+            for (int i = 0; i < 4; ++i) {
+                a[i] = *(const float *)(sA + (wr + 16 * i + (l & 15)) * kGLds + kb);
+                b[i] = *(const float *)(sB + (wc + 16 * i + (l & 15)) * kGLds + kb);
             }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
     // epilogue: element v of lane l in tile (i, j) is Z[row 4 (l / 16) + v][col l % 16]
@@ -242,20 +244,7 @@ __global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int col = n0 + wc + 16 * j + (l & 15);
-                if (col < g.D) {
-                    const float z = acc[i][j][v];
-                    const float zz = z * z;
-                    if (g.kind == K_RASTRIGIN) {
-                        g1 += zz - 10.f * cos2pi(z) + 10.f;
-                        g2 += zz;
-                    } else if (g.kind == K_ACKLEY) {
-                        g1 += zz;
-                        g2 += cos2pi(z);
-                    } else {
-                        g1 += zz;
-                        g2 += zz;
-                    }
-                }
+                obj_terms<KIND>(acc[i][j][v], col < g.D, g1, g2);
             }
             g1 = group_sum<16>(g1);
             g2 = group_sum<16>(g2);
@@ -263,6 +252,171 @@ __global__ __launch_bounds__(256) void gemm_obj(GemmRun g) {
             if ((l & 15) == 0 && srow < nrows) {
                 g.P1[(size_t)srow * NH + half] = g1;
                 g.P2[(size_t)srow * NH + half] = g2;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 estimate product Z = bf16(y - o) bf16(M)^T with binary32 accumulation
+// on the 16 x 16 x 32 BF16 matrix cores, the same epilogue partials as the
+// binary32 product.  Workgroup tile 256 rows x 128 columns: wavefront w owns
+// rows 64 w .. 64 w + 63 (4 x 8 MFMA tiles, 128 accumulators per lane) and
+// reads its A rows from global memory straight into fragment registers, one
+// chunk ahead; the 128 rows of M the four wavefronts share are staged
+// through LDS in chunks of 128 K (two buffers, one barrier per chunk).  The
+// tiles of a row block are placed on one XCD (workgroup b runs on XCD b mod
+// 8), so the block's A rows are fetched from HBM once into that XCD's L2.
+// ---------------------------------------------------------------------------
+struct BChunkA {
+    u32x4 v[4][kBKS];   // [row tile][k-step]: 8 BF16 of K per lane and step
+};
+
+// A of chunk kc (K elements) for the lane's four row tiles: byte offsets
+// aoff[i] from the uniform base, 16 bytes per k-step.
+__device__ __forceinline__ void bf16_load_a(const unsigned char *abase, const uint32_t (&aoff)[4],
+                                            int kc, BChunkA &a) {
+    const unsigned char *b = abase + (size_t)kc * 2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int s = 0; s < kBKS; ++s) a.v[i][s] = *(const u32x4 *)(b + aoff[i] + 64 * s);
+}
+
+// Prefetch depths of the BF16 product, in chunks: A rows come from HBM (or
+// from the L2 after the first of a row block's workgroups), M's rows from
+// the L2.
+constexpr int kBDA = 3, kBDB = 2;
+
+// One K chunk c of the BF16 product (A in a[c % 4], M in LDS buffer c & 1).
+// Issued first: the A loads of chunk c + kBDA into a[(c + kBDA) % 4] and the
+// M loads of chunk c + kBDB into bs[c % 2]; after the MFMA work, M of chunk
+// c + 1 (loaded one chunk earlier, in bs[(c + 1) % 2]) goes to LDS buffer
+// (c + 1) & 1.  Chunks past the end re-read the last one (unused).
+template <int PH>
+__device__ __forceinline__ void bf16_chunk(int c, int nc, const unsigned char *abase,
+                                           const uint32_t (&aoff)[4],
+                                           const unsigned char *bsrc, size_t rstride,
+                                           unsigned char *bdst, const unsigned char *bfr,
+                                           BChunkA (&a)[4], u32x4 (&bs)[2][kBQ],
+                                           f32x4 (&acc)[4][8]) {
+    {
+        const int cb = min(c + kBDB, nc - 1);
+#pragma unroll
+        for (int q = 0; q < kBQ; ++q)
+            bs[PH % 2][q] =
+                *(const u32x4 *)(bsrc + (256 / kBU) * q * rstride + (size_t)cb * (kBK * 2));
+        bf16_load_a(abase, aoff, min(c + kBDA, nc - 1) * kBK, a[(PH + kBDA) % 4]);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the MFMA work
+    const BChunkA &cur = a[PH];
+    const unsigned char *sb = bfr + (PH & 1) * (kBN * kBLds);
+#pragma unroll
+    for (int s = 0; s < kBKS; ++s) {
+        // lane l: B[k = 32 s + 8 (l / 16) .. + 7][column 16 j + l % 16]
+        u32x4 bv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bv[j] = *(const u32x4 *)(sb + 16 * j * kBLds + 64 * s);
+        __builtin_amdgcn_sched_barrier(0);   // all eight reads in flight before the MFMAs
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, cur.v[i][s]), __builtin_bit_cast(bf16x8, bv[j]),
+                    acc[i][j], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    unsigned char *d = bdst + ((PH + 1) & 1) * (kBN * kBLds);
+#pragma unroll
+    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(d + (256 / kBU) * q * kBLds) = bs[(PH + 1) % 2][q];
+    __syncthreads();
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gemm_obj_bf16(
+    GemmRun g) {
+    extern __shared__ __align__(16) unsigned char gsm[];
+    const int nrows = g.rows;   // ranks (the BF16 product has no list form)
+    const int nM = (g.rows + kBM - 1) / kBM, nN = g.Np / kBN;
+    const int b = blockIdx.x;
+    int rb, nb;
+    if ((nM & 7) == 0) {
+        const int x = b & 7, idx = b >> 3;
+        rb = (idx / nN) * 8 + x;
+        nb = idx % nN;
+    } else {
+        rb = b / nN;
+        nb = b % nN;
+    }
+    const int m0 = rb * kBM, n0 = nb * kBN;
+    if (m0 >= nrows) return;   // the whole workgroup: no barrier is skipped
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+    // lane l: row 16 i + l % 16 of the wavefront's rows, K offset 8 (l / 16);
+    // rows past the end read the last row (their sums are not stored)
+    const unsigned char *abase = (const unsigned char *)g.Ab;
+    uint32_t aoff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = min(m0 + 64 * wave + 16 * i + (l & 15), nrows - 1);
+        aoff[i] = (uint32_t)row * (uint32_t)g.Kp * 2u + (uint32_t)(l >> 4) * 16u;
+    }
+    // M staging: thread tid moves 16-byte unit tid % kBU of rows
+    // (256 / kBU) q + tid / kBU
+    const size_t rstride = (size_t)g.Kp * 2;
+    const unsigned char *bsrc =
+        (const unsigned char *)g.B + (size_t)(n0 + tid / kBU) * rstride + (tid % kBU) * 16;
+    unsigned char *bdst = gsm + (tid / kBU) * kBLds + (tid % kBU) * 16;
+    // fragment reads: lane l reads row 16 j + l % 16 of the chunk at K 8 (l / 16)
+    const unsigned char *bfr = gsm + (l & 15) * kBLds + (l >> 4) * 16;
+    f32x4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nc = g.Kp / kBK;   // a multiple of 4: Kp is a multiple of 128
+    BChunkA a[4];
+    u32x4 bs[2][kBQ];
+    // prologue: A of chunks 0 .. kBDA - 1, M of chunk 0 into LDS buffer 0 and
+    // M of chunk 1 into bs[1]
+#pragma unroll
+    for (int q = 0; q < kBQ; ++q) {
+        bs[0][q] = *(const u32x4 *)(bsrc + (256 / kBU) * q * rstride);
+        bs[1][q] = *(const u32x4 *)(bsrc + (256 / kBU) * q * rstride + (size_t)kBK * 2);
+    }
+#pragma unroll
+    for (int c = 0; c < kBDA; ++c) bf16_load_a(abase, aoff, c * kBK, a[c]);
+#pragma unroll
+    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(bdst + (256 / kBU) * q * kBLds) = bs[0][q];
+    __syncthreads();
+    for (int c = 0; c < nc; c += 4) {
+        bf16_chunk<0>(c, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
+        bf16_chunk<1>(c + 1, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
+        bf16_chunk<2>(c + 2, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
+        bf16_chunk<3>(c + 3, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
+    }
+    // epilogue: element v of lane l in tile (i, j) is Z[row 4 (l / 16) + v][col l % 16];
+    // columns 0..63 and 64..127 of the tile give two half partials
+    const int NH = g.Np / 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int srow = m0 + 64 * wave + 16 * i + 4 * (l >> 4) + v;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float g1 = 0.f, g2 = 0.f;
+#pragma unroll
+                for (int j = 4 * h; j < 4 * h + 4; ++j) {
+                    const int col = n0 + 16 * j + (l & 15);
+                    obj_terms<KIND>(acc[i][j][v], col < g.D, g1, g2);
+                }
+                g1 = group_sum<16>(g1);
+                g2 = group_sum<16>(g2);
+                if ((l & 15) == 0 && srow < nrows) {
+                    g.P1[(size_t)srow * NH + n0 / 64 + h] = g1;
+                    g.P2[(size_t)srow * NH + n0 / 64 + h] = g2;
+                }
             }
         }
     }
@@ -466,17 +620,35 @@ static hipError_t launch_cand(const Params &p, const GemmBufs &w, int init, hipS
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_gemm(const GemmRun &g, bool bf16, hipStream_t s) {
-    const dim3 grid((unsigned)(g.Np / kGN), (unsigned)((g.rows + kGM - 1) / kGM)), block(256);
-    const void *fn = bf16 ? (const void *)gemm_obj<uint16_t> : (const void *)gemm_obj<float>;
-    const hipError_t ea =
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
+template <int KIND>
+static hipError_t launch_gemm_t(const GemmRun &g, bool bf16, hipStream_t s) {
+    if (bf16) {
+        if (g.list) return hipErrorInvalidValue;
+        const hipError_t ea = hipFuncSetAttribute((const void *)gemm_obj_bf16<KIND>,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  (int)kBLdsLaunch);
+        if (ea != hipSuccess) return ea;
+        const int nM = (g.rows + kBM - 1) / kBM, nN = g.Np / kBN;
+        hipLaunchKernelGGL(gemm_obj_bf16<KIND>, dim3((unsigned)(nM * nN)), dim3(256), kBLdsLaunch,
+                           s, g);
+        return hipGetLastError();
+    }
+    const hipError_t ea = hipFuncSetAttribute((const void *)gemm_obj_f32<KIND>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)kGemmLds);
     if (ea != hipSuccess) return ea;
-    if (bf16)
-        hipLaunchKernelGGL(gemm_obj<uint16_t>, grid, block, kGemmLds, s, g);
-    else
-        hipLaunchKernelGGL(gemm_obj<float>, grid, block, kGemmLds, s, g);
+    const dim3 grid((unsigned)(g.Np / kGN), (unsigned)((g.rows + kGM - 1) / kGM)), block(256);
+    hipLaunchKernelGGL(gemm_obj_f32<KIND>, grid, block, kGemmLds, s, g);
     return hipGetLastError();
+}
+
+static hipError_t launch_gemm(const GemmRun &g, bool bf16, hipStream_t s) {
+    switch (g.kind) {
+    case K_SPHERE: return launch_gemm_t<K_SPHERE>(g, bf16, s);
+    case K_RASTRIGIN: return launch_gemm_t<K_RASTRIGIN>(g, bf16, s);
+    case K_ACKLEY: return launch_gemm_t<K_ACKLEY>(g, bf16, s);
+    default: return hipErrorInvalidValue;   // the GEMM form takes the rotated objectives above
+    }
 }
 
 hipError_t launch_gemm_stage(const Params &p, const GemmBufs &w, int init, int stage,
