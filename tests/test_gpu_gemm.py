@@ -92,3 +92,25 @@ def test_precision_pipeline_full_size():
         p = O.Problem(dim=w.dim, pop=w.pop, lb=w.lb, ub=w.ub, kind="ackley", shift=w.shift,
                       rot=w.rot)
         assert abs(f - p.objective(x)) <= 1e-10 * max(1.0, abs(f))
+
+
+def test_bf16_settled_rejections_keep_parents():
+    """Sphere at D 520: the bound is a fixed fraction of the fitness, so
+    candidates far worse than their parents are rejected on the BF16
+    estimate alone (the parent row and fitness carried over without a
+    binary32 re-score).  The run still equals the binary32 form's."""
+    apo = need_gpu()
+    print("[gemm] bf16 vs fp32 D520 sphere, settled rejections", flush=True)
+    w, a, b = _pair(apo, 520, 256, "sphere", 40, 11)
+    with a, b:
+        for _ in range(4):
+            a.run(10)
+            b.run(10)
+            Xa, Fa, ta = a.get_state()
+            Xb, Fb, tb = b.get_state()
+            assert ta == tb
+            assert np.array_equal(Xa, Xb) and np.array_equal(Fa, Fb)
+        rescored, estimated = b.precision_stats()
+        print(f"[gemm] re-scored {rescored} of {estimated}", flush=True)
+        assert estimated == 40 * 256
+        assert 0 < rescored < estimated
