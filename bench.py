@@ -26,31 +26,39 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tile_f32_rotated_rastrigin_ps4096_d100.md")
-KERNEL_SOURCES = ["apo_step.hpp", "apo_device.hpp", "apo_step_tile_f32.hip"]
+# Counter summaries (HBM bytes per launch of a workload's dominant kernel)
+# and the kernel sources they were taken on.
+TRAFFIC = {
+    "c2": ("traffic_step_tile_f32_rotated_rastrigin_ps4096_d100.md",
+           ["apo_step.hpp", "apo_device.hpp", "apo_step_tile_f32.hip"]),
+    "c5": ("traffic_gemm_obj_bf16_rotated_ackley_ps8192_d1000.md",
+           ["apo_gemm.hip", "apo_step.hpp", "apo_device.hpp"]),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources) -> str:
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources:
         with open(os.path.join(ROOT, "paper_2510_14982_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the step kernel from the committed counter
-    summary, only if it was taken on the current kernel source."""
+def measured_traffic(workload):
+    """HBM bytes per launch of the workload's dominant kernel from the
+    committed counter summary, only if it was taken on the current kernel
+    source."""
+    fname, sources = TRAFFIC[workload]
     fields = {}
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", fname)) as f:
             for line in f:
                 if ":" in line and not line.startswith((" ", "|", "#")):
                     k, v = line.split(":", 1)
                     fields[k.strip()] = v.strip()
     except OSError:
         return None
-    if fields.get("kernel_source_hash") != kernel_source_hash():
+    if fields.get("kernel_source_hash") != kernel_source_hash(sources):
         return None
     try:
         return int(fields["hbm_bytes_per_launch"])
@@ -363,7 +371,7 @@ def precision_run(torch, apo, args):
                        "product_TFLOP_per_s": flops / (st["product"] * 1e-6) / 1e12}
     b, fp = forms["bf16"], forms["fp32"]
     ach = b["product_TFLOP_per_s"]
-    print(json.dumps({
+    out = {
         "metric": "fitness evals/sec, BF16 precision pipeline vs binary32 form (ps 8192, D 1000)",
         "value": b["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": steps, "warmup": 16,
         "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -374,10 +382,16 @@ def precision_run(torch, apo, args):
         "equal_final_fitness": b["final_best_f_fp64"] == fp["final_best_f_fp64"],
         "forms": forms,
         "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA_TFLOPS, "traffic": None,
-                     "kernel": "gemm_obj<bf16> (z = M (y - o) estimate with fused objective sums)",
-                     "algorithmic_flops_per_launch": flops},
-    }), flush=True)
+                     "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA_TFLOPS,
+                     "traffic": measured_traffic("c5"),
+                     "kernel": "gemm_obj_bf16<ACKLEY> (BF16 estimate of z = M (y - o) with "
+                               "fused objective sums)",
+                     "algorithmic_flops_per_launch": flops,
+                     "algorithmic_bytes_per_launch": (w.pop + 1024) * 1024 * 2},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -488,7 +502,7 @@ def main():
         out["roofline"] = {
             "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-            "traffic": measured_traffic() if args.workload == "c2" else None,
+            "traffic": measured_traffic("c2") if args.workload == "c2" else None,
             "kernel": "step_tile<float> (update + clamp + z = M(y-o) on MFMA + select)",
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_alg,
             "hbm_frac_at_algorithmic_bytes": bytes_alg / (step_us * 1e-6) / 1e9 / PEAK_HBM_GBS}
