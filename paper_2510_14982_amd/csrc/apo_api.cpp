@@ -72,7 +72,7 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     const bool gf = gemm_form(dim, o);
     L.rotp = (o.objective.rot && !gf) ? take((size_t)L.Ks * L.Nt * 64 * es) : 0;
     if (gf) {
-        L.Kp = (dim + 127) / 128 * 128;   // whole product chunks of 256 bytes (BF16)
+        L.Kp = (dim + 127) / 128 * 128;   // K in groups of four 32-K chunks (BF16 product)
         L.Np = (dim + 127) / 128 * 128;
         const bool bf = o.precision == APO_BF16;
         L.gYr = take((size_t)pop * L.Dp * 4);

@@ -544,16 +544,20 @@ __global__ __launch_bounds__(256) void gemm_classify(Params p, GemmRun g, GemmBu
 }
 
 // Binary64 re-score of one row (the elite): z = M (x - o) and the objective
-// in binary64 (one workgroup of 256 threads).  out[0] receives F.
-__global__ __launch_bounds__(256) void elite_f64(Params p, GemmBufs w, const double *x,
-                                                 double *out) {
-    __shared__ double red[2][256];
-    const int D = p.dim;
+// in binary64, one workgroup of 16 wavefronts.  Wavefront w takes outputs
+// n = w, w + 16, ...; its lanes run over k (coalesced rows of M) and the
+// row is summed by the fixed butterfly; the per-wavefront sums are added in
+// wavefront order.  out[0] receives F.
+__global__ __launch_bounds__(1024) void elite_f64(Params p, GemmBufs w, const double *x,
+                                                  double *out) {
+    __shared__ double red[2][16];
+    const int D = p.dim, wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     double s1 = 0.0, s2 = 0.0;
-    for (int n = threadIdx.x; n < D; n += 256) {
+    for (int n = wave; n < D; n += 16) {
         const double *m = w.Md + (size_t)n * D;
         double z = 0.0;
-        for (int k = 0; k < D; ++k) z += m[k] * (x[k] - w.o64[k]);
+        for (int k = l; k < D; k += 64) z += m[k] * (x[k] - w.o64[k]);
+        z = group_sum<64>(z);
         if (p.kind == K_RASTRIGIN) {
             s1 += z * z - 10.0 * cos(2.0 * kPi * z) + 10.0;
         } else if (p.kind == K_ACKLEY) {
@@ -563,12 +567,14 @@ __global__ __launch_bounds__(256) void elite_f64(Params p, GemmBufs w, const dou
             s1 += z * z;
         }
     }
-    red[0][threadIdx.x] = s1;
-    red[1][threadIdx.x] = s2;
+    if (l == 0) {
+        red[0][wave] = s1;
+        red[1][wave] = s2;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double a = 0.0, b = 0.0;
-        for (int i = 0; i < 256; ++i) {
+        for (int i = 0; i < 16; ++i) {
             a += red[0][i];
             b += red[1][i];
         }
@@ -687,7 +693,7 @@ hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStr
 
 hipError_t launch_elite_f64(const Params &p, const GemmBufs &w, const double *x, double *out,
                             hipStream_t s) {
-    hipLaunchKernelGGL(elite_f64, dim3(1), dim3(256), 0, s, p, w, x, out);
+    hipLaunchKernelGGL(elite_f64, dim3(1), dim3(1024), 0, s, p, w, x, out);
     return hipGetLastError();
 }
 
