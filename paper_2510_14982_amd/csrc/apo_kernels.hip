@@ -87,8 +87,19 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
     // issued without waiting for it)
     const int t = __hip_atomic_load(&p.ctrl->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
 
+    // The first pass's key loads and the ranked protozoa's own fitness are
+    // all issued before the barrier, so the kernel waits for memory once
+    // (an index past the end reads the last element and is then replaced by
+    // the padding key).
+    T fj[kRankJ];
+#pragma unroll
+    for (int u = 0; u < kRankJ; ++u) {
+        const int j = 256 * u + tid;
+        fj[u] = F[j < ps ? j : ps - 1];
+    }
+    T fi = T(0);
     if (tid < kRankPer) {
-        const T fi = F[i0 + tid < ps ? i0 + tid : ps - 1];
+        fi = F[i0 + tid < ps ? i0 + tid : ps - 1];
         const uint64_t k = RankKey<T>::make(fi, i0 + tid);
         s_ki[tid] = i0 + tid < ps ? k : ~0ull;
     }
@@ -101,13 +112,12 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
     for (int q = 0; q < kRankPer; ++q) ki[q] = s_ki[q];
 
     for (int base = 0; base < ps; base += 256 * kRankJ) {
-        // all loads issued before any key is formed (an index past the end
-        // reads the last element and is then replaced by the padding key)
-        T fj[kRankJ];
+        if (base > 0) {   // further passes (ps above 4096)
 #pragma unroll
-        for (int u = 0; u < kRankJ; ++u) {
-            const int j = base + 256 * u + tid;
-            fj[u] = F[j < ps ? j : ps - 1];
+            for (int u = 0; u < kRankJ; ++u) {
+                const int j = base + 256 * u + tid;
+                fj[u] = F[j < ps ? j : ps - 1];
+            }
         }
         // the last wavefront opens the iteration while its loads are in flight
         if (base == 0 && wave == 3) open_iteration(p, t, s_keys, &s_mdr);
@@ -139,7 +149,7 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
     if (tid < kRankPer && i0 + tid < ps) {
         const int rank = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
         p.perm[rank] = i0 + tid;
-        ((T *)p.Fs)[rank] = F[i0 + tid];
+        ((T *)p.Fs)[rank] = fi;
         // Dr of Algorithm 1: rank r belongs iff pi(r) < |Dr|
         Subset drs;
         subset_shape(drs, (uint32_t)ps);
