@@ -25,7 +25,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Offsets of every device array inside the workspace (bytes, 256-aligned).
 struct Layout {
-    size_t gYr, gAb, gan, gP1, gP2, glist, gstat, gcount, gtot, gMb, gMf, gMd, go64;   // GEMM form
+    size_t gYr, gAb, gan, gP1, gP2, glist, gstat, gcount, gtot, gMb, gMf, gMd, go64, gz64;   // GEMM form
     int Kp, Np;
     size_t X[2], F, perm, Fs, drf, ctrl, p_ah, fscale, cnear, p_dr, lb, ub, shift, rotp, htab, hist,
         best, trY, trF, trOp, total;
@@ -88,6 +88,7 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
         L.gMf = take((size_t)L.Np * L.Kp * 4);
         L.gMd = take((size_t)dim * dim * 8);
         L.go64 = take((size_t)dim * 8);
+        L.gz64 = take((size_t)dim * 8);
     }
     L.htab = is_threshold(o.objective.kind) ? take(3 * 257 * 8) : 0;
     L.hist = is_threshold(o.objective.kind) ? take(256 * 8) : 0;
@@ -581,6 +582,7 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         g.Mf = (const float *)(ws + L.gMf);
         g.Md = (const double *)(ws + L.gMd);
         g.o64 = (const double *)(ws + L.go64);
+        g.z64 = (double *)(ws + L.gz64);
         g.Kp = L.Kp;
         g.Np = L.Np;
         g.bf16 = opt->precision == APO_BF16 ? 1 : 0;

@@ -543,21 +543,27 @@ __global__ __launch_bounds__(256) void gemm_classify(Params p, GemmRun g, GemmBu
     }
 }
 
-// Binary64 re-score of one row (the elite): z = M (x - o) and the objective
-// in binary64, one workgroup of 16 wavefronts.  Wavefront w takes outputs
-// n = w, w + 16, ...; its lanes run over k (coalesced rows of M) and the
-// row is summed by the fixed butterfly; the per-wavefront sums are added in
-// wavefront order.  out[0] receives F.
-__global__ __launch_bounds__(1024) void elite_f64(Params p, GemmBufs w, const double *x,
-                                                  double *out) {
+// Binary64 re-score of one row (the elite), in two launches.  elite_z: one
+// wavefront per output n, lanes over k (rows of M read contiguously), the
+// row summed by the fixed butterfly: z64[n] = (M (x - o))_n.
+__global__ __launch_bounds__(64) void elite_z(Params p, GemmBufs w, const double *x) {
+    const int D = p.dim, n = blockIdx.x, l = threadIdx.x;
+    const double *m = w.Md + (size_t)n * D;
+    double z = 0.0;
+    for (int k = l; k < D; k += 64) z += m[k] * (x[k] - w.o64[k]);
+    z = group_sum<64>(z);
+    if (l == 0) w.z64[n] = z;
+}
+
+// elite_f: the objective from z64 (one workgroup of 1024 threads, thread i
+// takes n = i, i + 1024, ...; per-wavefront butterflies, then the sixteen
+// wavefront sums in order).  out[0] receives F.
+__global__ __launch_bounds__(1024) void elite_f(Params p, GemmBufs w, double *out) {
     __shared__ double red[2][16];
     const int D = p.dim, wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     double s1 = 0.0, s2 = 0.0;
-    for (int n = wave; n < D; n += 16) {
-        const double *m = w.Md + (size_t)n * D;
-        double z = 0.0;
-        for (int k = l; k < D; k += 64) z += m[k] * (x[k] - w.o64[k]);
-        z = group_sum<64>(z);
+    for (int n = threadIdx.x; n < D; n += 1024) {
+        const double z = w.z64[n];
         if (p.kind == K_RASTRIGIN) {
             s1 += z * z - 10.0 * cos(2.0 * kPi * z) + 10.0;
         } else if (p.kind == K_ACKLEY) {
@@ -567,6 +573,8 @@ __global__ __launch_bounds__(1024) void elite_f64(Params p, GemmBufs w, const do
             s1 += z * z;
         }
     }
+    s1 = group_sum<64>(s1);
+    s2 = group_sum<64>(s2);
     if (l == 0) {
         red[0][wave] = s1;
         red[1][wave] = s2;
@@ -693,7 +701,10 @@ hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStr
 
 hipError_t launch_elite_f64(const Params &p, const GemmBufs &w, const double *x, double *out,
                             hipStream_t s) {
-    hipLaunchKernelGGL(elite_f64, dim3(1), dim3(1024), 0, s, p, w, x, out);
+    hipLaunchKernelGGL(elite_z, dim3((unsigned)p.dim), dim3(64), 0, s, p, w, x);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(elite_f, dim3(1), dim3(1024), 0, s, p, w, out);
     return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct GemmBufs {
     const float *Mf;      // [Np][Kp] M in binary32
     const double *Md;     // [dim][dim] M in binary64 (elite re-score)
     const double *o64;    // [dim] shift in binary64
+    double *z64;          // [dim] z of the elite re-score
     int32_t Kp, Np;       // K and N padded to 128
     int32_t bf16;         // 1: BF16 estimate + binary32 re-score
 };
