@@ -110,10 +110,30 @@ def f_tolerance(p, y, precision):
     return 1e-5 * scale + 1e-6 * rot_err + 1e-6
 
 
-def y_tolerance(x, y, precision):
+def y_tolerance(x, y, precision, mag=0.0):
+    """Candidate tolerance: relative to the row and the move, plus a term in
+    the largest operand the coordinate is computed from (mag): rounding in
+    Eqs. (1), (2), (6)-(10) is relative to the bounds and the neighbour rows,
+    which can be far larger than the result."""
     if precision == "fp64":
-        return 64 * EPS64 * (np.abs(x) + np.abs(y - x) + 1.0)
-    return 1e-5 * (np.abs(x) + np.abs(y - x)) + 1e-6
+        return 64 * EPS64 * (np.abs(x) + np.abs(y - x) + 1.0 + mag)
+    return 1e-5 * (np.abs(x) + np.abs(y - x)) + 1e-6 * mag + 1e-6
+
+
+def operand_magnitude(p, X, tr):
+    """Per candidate coordinate, the largest operand magnitude its formula
+    reads: the bounds for dormancy and reproduction (Eqs. (1), (2)), the own
+    row and the neighbour rows for the foraging modes (Eqs. (6)-(10))."""
+    bnd = np.maximum(np.abs(np.broadcast_to(np.asarray(p.lb, float), (p.dim,))),
+                     np.abs(np.broadcast_to(np.asarray(p.ub, float), (p.dim,))))
+    mag = np.abs(X).astype(np.float64)
+    forage = tr.op >= 2
+    for c in range(tr.nb.shape[1]):
+        ids = tr.nb[:, c]
+        ok = forage & (ids >= 0)
+        mag[ok] = np.maximum(mag[ok], np.abs(X[ids[ok]]))
+    mag[~forage] = np.maximum(mag[~forage], bnd)
+    return mag
 
 
 def compare_step(g, p, t, X, F, precision, exact_dr=True):
@@ -138,7 +158,8 @@ def compare_step(g, p, t, X, F, precision, exact_dr=True):
         clear = frac > 1e-4
         assert np.array_equal(np.rint(Yg)[clear], np.rint(tr.Y)[clear])
     else:
-        tol = y_tolerance(X, tr.Y, precision)
+        mag = operand_magnitude(p, X, tr)
+        tol = y_tolerance(X, tr.Y, precision, mag)
         bad = np.abs(Yg - tr.Y) > tol
         assert not bad.any(), f"candidates differ at {np.argwhere(bad)[:5].tolist()}"
         # dormancy / reproduction rows have no transcendental: exact in FP64
@@ -159,9 +180,10 @@ def compare_step(g, p, t, X, F, precision, exact_dr=True):
     mismatch = (acc_g != tr.accepted) & ~near
     assert not mismatch.any(), f"selection differs at ids {np.where(mismatch)[0][:5]}"
     same = ~near
+    mag = operand_magnitude(p, X, tr) if p.kind not in ("kapur", "otsu") else np.zeros_like(X)
     for i in np.where(same)[0]:
         if tr.accepted[i]:
-            assert np.all(np.abs(Xg[i] - Xo[i]) <= y_tolerance(X[i], Xo[i], precision))
+            assert np.all(np.abs(Xg[i] - Xo[i]) <= y_tolerance(X[i], Xo[i], precision, mag[i]))
             assert abs(Fg[i] - Fo[i]) <= ftol[i]
         else:
             assert np.array_equal(Xg[i], X[i]) and Fg[i] == F[i]

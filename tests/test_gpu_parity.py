@@ -39,6 +39,9 @@ STEP_CASES = [
                                 precision="fp32"), 1, 1000),
     ("c2_full_size_late", dict(dim=100, pop=4096, kind="rastrigin", rotated=True,
                                precision="fp32"), 640, 1000),
+    # the precision configuration's shape in binary32: the GEMM form as bench.py times it
+    ("c5_full_size_fp32_gemm", dict(dim=1000, pop=8192, kind="ackley", rotated=True,
+                                    precision="fp32"), 1, 2000),
     # many rank-sort splits with a ragged last block
     ("large_pop_ragged_fp64", dict(dim=10, pop=5000, kind="rastrigin"), 3, 10),
     ("large_pop_fp32_d3", dict(dim=3, pop=8192, kind="sphere", precision="fp32",
