@@ -114,3 +114,25 @@ def test_bf16_settled_rejections_keep_parents():
         print(f"[gemm] re-scored {rescored} of {estimated}", flush=True)
         assert estimated == 40 * 256
         assert 0 < rescored < estimated
+
+
+@pytest.mark.parametrize("dim,pop", [(1, 2), (17, 3), (129, 300)])
+def test_bf16_form_ragged_shapes(dim, pop):
+    """The BF16 form at ragged sizes (K and N padding, a partial row block,
+    more than one row block): finite fitness, rows in bounds, the stored
+    fitness equal to the objective of the stored row within binary32
+    rounding, and the elite re-scored in binary64."""
+    apo = need_gpu()
+    print(f"[gemm] bf16 ragged D{dim} ps{pop}", flush=True)
+    g, p = make_pair(apo, dim=dim, pop=pop, kind="rastrigin", rotated=True, precision="bf16",
+                     max_iter=6, seed=5, pf_max=0.5)
+    with g:
+        g.run(6)
+        X, F, t = g.get_state()
+        assert t == 6 and np.all(np.isfinite(F))
+        assert np.all(X >= p.lb) and np.all(X <= p.ub)
+        for i in range(0, pop, max(1, pop // 7)):
+            fo = p.objective(X[i])
+            assert abs(F[i] - fo) <= 1e-4 * (abs(fo) + 1.0), i
+        x, f, _ = g.best()
+        assert abs(f - p.objective(x)) <= 1e-10 * max(1.0, abs(f))

@@ -39,6 +39,12 @@ STEP_CASES = [
                                 precision="fp32"), 1, 1000),
     ("c2_full_size_late", dict(dim=100, pop=4096, kind="rastrigin", rotated=True,
                                precision="fp32"), 640, 1000),
+    # the GEMM form at its smallest: just above the dimension threshold, a
+    # handful of protozoa (one partial row tile, ragged K and N padding)
+    ("gemm_form_d513_pop5", dict(dim=513, pop=5, kind="rastrigin", rotated=True,
+                                 precision="fp32", pf_max=0.5), 2, 10),
+    ("gemm_form_d700_pop2_ackley", dict(dim=700, pop=2, kind="ackley", rotated=True,
+                                        precision="fp32"), 1, 5),
     # the precision configuration's shape in binary32: the GEMM form as bench.py times it
     ("c5_full_size_fp32_gemm", dict(dim=1000, pop=8192, kind="ackley", rotated=True,
                                     precision="fp32"), 1, 2000),
