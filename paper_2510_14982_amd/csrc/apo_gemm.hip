@@ -353,7 +353,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (m0 >= nrows) return;   // the whole workgroup: no barrier is skipped
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
     // lane l: row 16 i + l % 16 of the wavefront's rows, K offset 8 (l / 16);
-    // rows past the end read the last row (their sums are not stored)
+    // rows past the end read the last row (their sums are not stored).  The
+    // 32-bit byte offsets hold: at most 65536 rows of 1024 BF16 values (128 MiB).
     const unsigned char *abase = (const unsigned char *)g.Ab;
     uint32_t aoff[4];
 #pragma unroll
