@@ -15,6 +15,7 @@ on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -41,10 +42,16 @@ TRAFFIC = {
 
 
 def kernel_source_hash(sources) -> str:
+    """Hash of the kernel sources' code: comments and blank lines are left
+    out, so a counter summary stays valid across comment-only edits."""
     h = hashlib.sha256()
     for name in sources:
-        with open(os.path.join(ROOT, "paper_2510_14982_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2510_14982_amd", "csrc", name)) as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
