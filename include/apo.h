@@ -164,7 +164,8 @@ int apo_set_state(apo_t *h, const double *X, const double *F, int32_t iter);
 int apo_get_trace(apo_t *h, double *Y, double *Fy, int32_t *op, int32_t *perm);
 
 /* Per-kernel timing of n more iterations (n >= 1, clipped like apo_run),
- * measured with HIP events on the handle's stream around each launch:
+ * measured with HIP events that each launch records itself at the kernel's
+ * start and end (kernel execution alone, launch gaps excluded):
  * avg_us[0] rank sort, avg_us[1] step (update + evaluation + selection).
  * Returns the number of iterations executed or a status. */
 int apo_time_kernels(apo_t *h, int32_t n, double *avg_us);
@@ -177,11 +178,11 @@ int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint32_t *d_hist, void *s
 
 /* Stage times of a handle whose step runs in the GEMM form (rotated
  * objectives above 512 dimensions in binary32, and every APO_BF16 handle):
- * n more iterations (clipped like apo_run), HIP events on the handle's
- * stream around each launch, average microseconds per iteration into
- * us[6]: [0] candidates, [1] product (BF16 estimate, or binary32), [2] BF16
- * classification, [3] binary32 re-score product, [4] selection, [5] sort
- * ([2] and [3] are ~0 in binary32).  Returns n, or APO_E_STATE for a handle
+ * n more iterations (clipped like apo_run), HIP events recorded by each
+ * launch at the kernel's start and end, average microseconds per iteration
+ * into us[6]: [0] candidates, [1] product (BF16 estimate, or binary32), [2]
+ * BF16 classification, [3] binary32 re-score product, [4] selection, [5]
+ * sort ([2] and [3] are 0 in binary32).  Returns n, or APO_E_STATE for a handle
  * of another form. */
 int apo_time_gemm_stages(apo_t *h, int32_t iters, double *us);
 

@@ -184,7 +184,7 @@ struct apo {
     hipGraph_t graph[2];          // [0]: one iteration, [1]: kGraphBlock iterations
     hipGraphExec_t graph_exec[2];
     bool graph_tried;
-    hipEvent_t ev[3];
+    hipEvent_t ev[4];
     bool have_events;
     bool batch_view;      // a member of a batch: stepped only through the batch
 };
@@ -474,7 +474,7 @@ static int destroy_impl(apo_t *h) {
         if (h->graph[i]) (void)hipGraphDestroy(h->graph[i]);
     }
     if (h->have_events)
-        for (int i = 0; i < 3; ++i) (void)hipEventDestroy(h->ev[i]);
+        for (int i = 0; i < 4; ++i) (void)hipEventDestroy(h->ev[i]);
     if (h->stream && !h->poisoned) (void)hipStreamSynchronize(h->stream);
     if (h->own_ws && h->ws) (void)hipFree(h->ws);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -796,20 +796,24 @@ int apo_time_kernels(apo_t *h, int32_t iters, double *avg_us) {
     if (iters < n) n = iters;
     if (n <= 0) return APO_E_DONE;
     if (!h->have_events) {
-        for (int i = 0; i < 3; ++i) APO_HIP(h, hipEventCreate(&h->ev[i]));
+        for (int i = 0; i < 4; ++i) APO_HIP(h, hipEventCreate(&h->ev[i]));
         h->have_events = true;
     }
+    // each launch records its own start and end events (kernel execution
+    // alone, as a kernel trace measures it)
+    Params pr = h->p, ps = h->p;
+    pr.ev_start = h->ev[0];
+    pr.ev_stop = h->ev[1];
+    ps.ev_start = h->ev[2];
+    ps.ev_stop = h->ev[3];
     double sum_rank = 0.0, sum_step = 0.0;
     for (int32_t i = 0; i < n; ++i) {
-        APO_HIP(h, hipEventRecord(h->ev[0], h->stream));
-        APO_HIP(h, apok::launch_rank(h->p, h->fp64, h->stream));
-        APO_HIP(h, hipEventRecord(h->ev[1], h->stream));
-        APO_HIP(h, apok::launch_step(h->p, h->fp64, h->stream));
-        APO_HIP(h, hipEventRecord(h->ev[2], h->stream));
-        APO_HIP(h, hipEventSynchronize(h->ev[2]));
+        APO_HIP(h, apok::launch_rank(pr, h->fp64, h->stream));
+        APO_HIP(h, apok::launch_step(ps, h->fp64, h->stream));
+        APO_HIP(h, hipEventSynchronize(h->ev[3]));
         float a = 0.f, b = 0.f;
         APO_HIP(h, hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
-        APO_HIP(h, hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
+        APO_HIP(h, hipEventElapsedTime(&b, h->ev[2], h->ev[3]));
         sum_rank += a;
         sum_step += b;
         ++h->t;
@@ -826,26 +830,34 @@ int apo_time_gemm_stages(apo_t *h, int32_t iters, double *us) {
     int32_t n = h->T - h->t;
     if (iters < n) n = iters;
     if (n <= 0) return APO_E_DONE;
-    hipEvent_t ev[7];
-    for (int i = 0; i < 7; ++i)
+    // launch order: sort, then stages 0..4; each launch records its own
+    // start and end events (kernel execution alone)
+    constexpr int kL = 6;
+    hipEvent_t ev[2 * kL];
+    for (int i = 0; i < 2 * kL; ++i)
         if (hipEventCreate(&ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
             return APO_E_DEVICE;
         }
-    double sum[6] = {0, 0, 0, 0, 0, 0};
+    const bool bf16 = h->p.gb.bf16 != 0;
+    Params q[kL];
+    for (int k = 0; k < kL; ++k) {
+        q[k] = h->p;
+        q[k].ev_start = ev[2 * k];
+        q[k].ev_stop = ev[2 * k + 1];
+    }
+    double sum[kL] = {0, 0, 0, 0, 0, 0};
     int rc = APO_OK;
     for (int32_t it = 0; it < n && rc == APO_OK; ++it) {
-        bool ok = hipEventRecord(ev[0], h->stream) == hipSuccess &&
-                  apok::launch_rank(h->p, h->fp64, h->stream) == hipSuccess &&
-                  hipEventRecord(ev[1], h->stream) == hipSuccess;
+        bool ok = apok::launch_rank(q[0], h->fp64, h->stream) == hipSuccess;
         for (int st = 0; ok && st < 5; ++st)
-            ok = apok::launch_gemm_stage(h->p, h->p.gb, 0, st, h->stream) == hipSuccess &&
-                 hipEventRecord(ev[2 + st], h->stream) == hipSuccess;
-        ok = ok && hipEventSynchronize(ev[6]) == hipSuccess;
-        float ms = 0.f;
-        for (int st = 0; ok && st < 6; ++st) {
-            ok = hipEventElapsedTime(&ms, ev[st], ev[st + 1]) == hipSuccess;
-            sum[st == 0 ? 5 : st - 1] += 1000.0 * ms;
+            ok = apok::launch_gemm_stage(q[1 + st], h->p.gb, 0, st, h->stream) == hipSuccess;
+        ok = ok && hipStreamSynchronize(h->stream) == hipSuccess;
+        for (int k = 0; ok && k < kL; ++k) {
+            if (!bf16 && (k == 3 || k == 4)) continue;   // no classification / re-score launch
+            float ms = 0.f;
+            ok = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess;
+            sum[k == 0 ? 5 : k - 1] += 1000.0 * ms;
         }
         if (!ok) {
             h->poisoned = true;
@@ -854,9 +866,9 @@ int apo_time_gemm_stages(apo_t *h, int32_t iters, double *us) {
             ++h->t;
         }
     }
-    for (int i = 0; i < 7; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 2 * kL; ++i) (void)hipEventDestroy(ev[i]);
     if (rc != APO_OK) return rc;
-    for (int i = 0; i < 6; ++i) us[i] = sum[i] / n;
+    for (int i = 0; i < kL; ++i) us[i] = sum[i] / n;
     return n;
 }
 

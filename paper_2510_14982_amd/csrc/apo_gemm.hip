@@ -623,10 +623,9 @@ static hipError_t launch_cand(const Params &p, const GemmBufs &w, int init, hipS
 #define APO_CAND(GG, CC)                                                                     \
     if (G == GG && NCH == CC) {                                                              \
         if (p.np == 1)                                                                       \
-            hipLaunchKernelGGL((gemm_cand<GG, CC, 1, BF16>), grid, block, 0, s, p, w, init); \
+            launch_k(p, gemm_cand<GG, CC, 1, BF16>, grid, block, 0, s, p, w, init);          \
         else                                                                                 \
-            hipLaunchKernelGGL((gemm_cand<GG, CC, kMaxNp, BF16>), grid, block, 0, s, p, w,  \
-                               init);                                                        \
+            launch_k(p, gemm_cand<GG, CC, kMaxNp, BF16>, grid, block, 0, s, p, w, init);     \
         return hipGetLastError();                                                            \
     }
     APO_CAND(4, 1) APO_CAND(8, 1) APO_CAND(16, 1) APO_CAND(32, 1) APO_CAND(64, 1)
@@ -636,7 +635,7 @@ static hipError_t launch_cand(const Params &p, const GemmBufs &w, int init, hipS
 }
 
 template <int KIND>
-static hipError_t launch_gemm_t(const GemmRun &g, bool bf16, hipStream_t s) {
+static hipError_t launch_gemm_t(const Params &p, const GemmRun &g, bool bf16, hipStream_t s) {
     if (bf16) {
         if (g.list) return hipErrorInvalidValue;
         const hipError_t ea = hipFuncSetAttribute((const void *)gemm_obj_bf16<KIND>,
@@ -644,8 +643,7 @@ static hipError_t launch_gemm_t(const GemmRun &g, bool bf16, hipStream_t s) {
                                                   (int)kBLdsLaunch);
         if (ea != hipSuccess) return ea;
         const int nM = (g.rows + kBM - 1) / kBM, nN = g.Np / kBN;
-        hipLaunchKernelGGL(gemm_obj_bf16<KIND>, dim3((unsigned)(nM * nN)), dim3(256), kBLdsLaunch,
-                           s, g);
+        launch_k(p, gemm_obj_bf16<KIND>, dim3((unsigned)(nM * nN)), dim3(256), kBLdsLaunch, s, g);
         return hipGetLastError();
     }
     const hipError_t ea = hipFuncSetAttribute((const void *)gemm_obj_f32<KIND>,
@@ -653,15 +651,15 @@ static hipError_t launch_gemm_t(const GemmRun &g, bool bf16, hipStream_t s) {
                                               (int)kGemmLds);
     if (ea != hipSuccess) return ea;
     const dim3 grid((unsigned)(g.Np / kGN), (unsigned)((g.rows + kGM - 1) / kGM)), block(256);
-    hipLaunchKernelGGL(gemm_obj_f32<KIND>, grid, block, kGemmLds, s, g);
+    launch_k(p, gemm_obj_f32<KIND>, grid, block, kGemmLds, s, g);
     return hipGetLastError();
 }
 
-static hipError_t launch_gemm(const GemmRun &g, bool bf16, hipStream_t s) {
+static hipError_t launch_gemm(const Params &p, const GemmRun &g, bool bf16, hipStream_t s) {
     switch (g.kind) {
-    case K_SPHERE: return launch_gemm_t<K_SPHERE>(g, bf16, s);
-    case K_RASTRIGIN: return launch_gemm_t<K_RASTRIGIN>(g, bf16, s);
-    case K_ACKLEY: return launch_gemm_t<K_ACKLEY>(g, bf16, s);
+    case K_SPHERE: return launch_gemm_t<K_SPHERE>(p, g, bf16, s);
+    case K_RASTRIGIN: return launch_gemm_t<K_RASTRIGIN>(p, g, bf16, s);
+    case K_ACKLEY: return launch_gemm_t<K_ACKLEY>(p, g, bf16, s);
     default: return hipErrorInvalidValue;   // the GEMM form takes the rotated objectives above
     }
 }
@@ -674,18 +672,18 @@ hipError_t launch_gemm_stage(const Params &p, const GemmBufs &w, int init, int s
     case 0:
         return bf16 ? launch_cand<true>(p, w, init, s) : launch_cand<false>(p, w, init, s);
     case 1:
-        return launch_gemm(gemm_run(p, w, bf16, false), bf16, s);
+        return launch_gemm(p, gemm_run(p, w, bf16, false), bf16, s);
     case 2:
         if (!bf16) return hipSuccess;
-        hipLaunchKernelGGL(gemm_classify, dim3((unsigned)((p.pop + 255) / 256)), sblock, 0, s, p,
-                           gemm_run(p, w, true, false), w);
+        launch_k(p, gemm_classify, dim3((unsigned)((p.pop + 255) / 256)), sblock, 0, s, p,
+                 gemm_run(p, w, true, false), w);
         return hipGetLastError();
     case 3:
         if (!bf16) return hipSuccess;
-        return launch_gemm(gemm_run(p, w, false, true), false, s);
+        return launch_gemm(p, gemm_run(p, w, false, true), false, s);
     case 4:
-        hipLaunchKernelGGL(gemm_select, sgrid, sblock, 0, s, p, gemm_run(p, w, false, false), w,
-                           init, bf16 ? 1 : 0);
+        launch_k(p, gemm_select, sgrid, sblock, 0, s, p, gemm_run(p, w, false, false), w, init,
+                 bf16 ? 1 : 0);
         return hipGetLastError();
     default:
         return hipErrorInvalidValue;

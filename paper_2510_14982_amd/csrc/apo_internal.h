@@ -2,6 +2,7 @@
 // the kernel launchers (apo_kernels.hip).  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -78,7 +79,21 @@ struct Params {
     void *trY;            // [pop][Dp]
     void *trF;            // [pop]
     int32_t *trOp;        // [pop]
+    // Host side only: when set, the launch records these events itself at
+    // the kernel's start and end (timing of the kernel's execution alone).
+    hipEvent_t ev_start, ev_stop;
 };
+
+// Launch through the dispatch-timed path when p carries timing events.
+template <typename F, typename... Args>
+inline void launch_k(const Params &p, F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                     Args... args) {
+    if (p.ev_start)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, p.ev_start, p.ev_stop, 0,
+                              args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
 
 // A batched launch: workgroup b runs block blocks[b].y of run blocks[b].x,
 // whose parameters are runs[blocks[b].x] (device arrays); lds is the

@@ -389,9 +389,9 @@ hipError_t launch_step(const Params &p, bool fp64, hipStream_t s) {
 hipError_t launch_rank(const Params &p, bool fp64, hipStream_t s) {
     const dim3 grid((unsigned)rank_blocks(p)), block(256);
     if (fp64)
-        hipLaunchKernelGGL(rank_kernel<double>, grid, block, 0, s, p);
+        launch_k(p, rank_kernel<double>, grid, block, 0, s, p);
     else
-        hipLaunchKernelGGL(rank_kernel<float>, grid, block, 0, s, p);
+        launch_k(p, rank_kernel<float>, grid, block, 0, s, p);
     return hipGetLastError();
 }
 

@@ -940,8 +940,7 @@ hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLa
             hipLaunchKernelGGL((step_tile_batch<T, GG, CC, NPMAX, TMM>), grid, block, lds, s, \
                                b->runs, b->blocks, init);                                    \
         else                                                                                 \
-            hipLaunchKernelGGL((step_tile<T, GG, CC, NPMAX, TMM>), grid, block, lds, s, p,   \
-                               init);                                                        \
+            launch_k(p, step_tile<T, GG, CC, NPMAX, TMM>, grid, block, lds, s, p, init);     \
         return hipGetLastError();                                                            \
     }
         APO_TILE(4, 1, 16) APO_TILE(8, 1, 16) APO_TILE(16, 1, 16) APO_TILE(32, 1, 16)
@@ -964,7 +963,7 @@ hipError_t launch_elem_t(const Params &p, int init, hipStream_t s, const BatchLa
             hipLaunchKernelGGL((step_elem_batch<T, GG, CC, NPMAX>), grid, block, 0, s,       \
                                b->runs, b->blocks, init);                                    \
         else                                                                                 \
-            hipLaunchKernelGGL((step_elem<T, GG, CC, NPMAX>), grid, block, 0, s, p, init);   \
+            launch_k(p, step_elem<T, GG, CC, NPMAX>, grid, block, 0, s, p, init);            \
         return hipGetLastError();                                                            \
     }
     APO_ELEM(4, 1) APO_ELEM(8, 1) APO_ELEM(16, 1) APO_ELEM(32, 1) APO_ELEM(64, 1)
