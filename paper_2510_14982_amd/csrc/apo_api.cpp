@@ -1040,7 +1040,10 @@ int apo_batch_create(int32_t n, const apo_run_desc *runs, const apo_batch_option
         }
         h->batch_view = true;
         // a batch fills the GPU with runs: fewer, fuller workgroups per run
-        h->p.rows = apok::tile_rows_wide(apok::lanes_for_dim(h->dim));
+        // (above 64 dimensions the tiled step takes 16 lanes per protozoan
+        // with two chunks each, so a workgroup holds 32 rows)
+        if (apok::lanes_for_dim(h->dim) == 32 && h->dim > 64) h->p.lanes = 16;
+        h->p.rows = apok::tile_rows_wide(h->p.lanes ? h->p.lanes : apok::lanes_for_dim(h->dim));
         h->p.rank_lds = h->pop <= apok::kRankLdsMax ? 1 : 0;
         b->runs.push_back(h);
     }

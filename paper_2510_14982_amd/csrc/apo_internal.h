@@ -57,6 +57,7 @@ struct Params {
     int32_t Nt, Ks;       // MFMA tiles: output column tiles of 16, k-steps of 4
     int32_t rows;         // ranks per workgroup of the tiled step: 16, or 512 / lanes
     int32_t rank_lds;     // 1: the sort stages the keys in LDS (pop <= 1024)
+    int32_t lanes;        // lanes per protozoan of the tiled step (0: lanes_for_dim)
     int32_t gemm;         // 1: the GEMM form of the step (gb)
     GemmBufs gb;
                           // (Ks padded to 32 or a multiple of 8; A and B zero there)
@@ -135,6 +136,10 @@ int step_shape(const Params &p, bool fp64);    // equal iff one kernel serves bo
 
 // Lanes per protozoan and 4-element chunks per lane used for a dimension.
 int lanes_for_dim(int dim);
+// The tiled step's lanes per protozoan and chunks per lane for a run (its
+// own lane count when set, else the dimension's); -1 chunks if none fits.
+int tile_lanes(const Params &p);
+int tile_chunks(const Params &p);
 // Largest population the LDS form of the sort takes.
 constexpr int kRankLdsMax = 1024;
 // Rows per workgroup of the wide tiled step for G lanes per protozoan.

@@ -356,6 +356,14 @@ int lanes_for_dim(int dim) {
     return g;
 }
 
+int tile_lanes(const Params &p) { return p.lanes > 0 ? p.lanes : lanes_for_dim(p.dim); }
+
+int tile_chunks(const Params &p) {
+    if (p.lanes <= 0) return chunks_for_dim(p.dim);
+    const int c = (p.dim + 4 * p.lanes - 1) / (4 * p.lanes);
+    return c <= 1 ? 1 : c <= 2 ? 2 : c <= 4 ? 4 : -1;
+}
+
 int chunks_for_dim(int dim) {
     const int g = lanes_for_dim(dim);
     const int c = (dim + 4 * g - 1) / (4 * g);
@@ -429,9 +437,10 @@ size_t step_lds_bytes(const Params &p, bool fp64) {
 
 // Instantiation key: precision, form, lanes, chunks and whether np > 1.
 int step_shape(const Params &p, bool fp64) {
-    return (fp64 ? 1 : 0) | (tile_form(p) ? 2 : 0) | (p.np > 1 ? 4 : 0) |
-           (lanes_for_dim(p.dim) << 3) | (chunks_for_dim(p.dim) << 12) |
-           ((tile_form(p) ? tile_rows(p) : 0) << 16);
+    const bool tf = tile_form(p);
+    return (fp64 ? 1 : 0) | (tf ? 2 : 0) | (p.np > 1 ? 4 : 0) |
+           ((tf ? tile_lanes(p) : lanes_for_dim(p.dim)) << 3) |
+           ((tf ? tile_chunks(p) : chunks_for_dim(p.dim)) << 12) | ((tf ? tile_rows(p) : 0) << 16);
 }
 
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s) {

@@ -920,7 +920,7 @@ inline size_t tile_lds_bytes(const Params &p, bool fp64) {
 // of them, lds the largest of theirs).
 template <typename T, int NPMAX>
 hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLaunch *b = nullptr) {
-    const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
+    const int G = tile_lanes(p), NCH = tile_chunks(p);
     if (NCH < 0) return hipErrorInvalidValue;
     {
         const int TMr = tile_rows(p);
@@ -945,7 +945,7 @@ hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLa
     }
         APO_TILE(4, 1, 16) APO_TILE(8, 1, 16) APO_TILE(16, 1, 16) APO_TILE(32, 1, 16)
         APO_TILE(64, 1, 16) APO_TILE(64, 2, 16)
-        APO_TILE(4, 1, 128) APO_TILE(8, 1, 64) APO_TILE(16, 1, 32)
+        APO_TILE(4, 1, 128) APO_TILE(8, 1, 64) APO_TILE(16, 1, 32) APO_TILE(16, 2, 32)
 #undef APO_TILE
         return hipErrorInvalidValue;
     }
