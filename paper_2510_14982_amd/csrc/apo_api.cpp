@@ -1040,9 +1040,9 @@ int apo_batch_create(int32_t n, const apo_run_desc *runs, const apo_batch_option
         }
         h->batch_view = true;
         // a batch fills the GPU with runs: fewer, fuller workgroups per run
-        // (above 64 dimensions the tiled step takes 16 lanes per protozoan
-        // with two chunks each, so a workgroup holds 32 rows)
-        if (apok::lanes_for_dim(h->dim) == 32 && h->dim > 64) h->p.lanes = 16;
+        // (above 32 dimensions the tiled step takes 8 lanes per protozoan
+        // with two or four chunks each, so a workgroup holds 64 rows)
+        if (h->dim > 32 && h->dim <= 128) h->p.lanes = 8;
         h->p.rows = apok::tile_rows_wide(h->p.lanes ? h->p.lanes : apok::lanes_for_dim(h->dim));
         h->p.rank_lds = h->pop <= apok::kRankLdsMax ? 1 : 0;
         b->runs.push_back(h);
