@@ -1040,9 +1040,16 @@ int apo_batch_create(int32_t n, const apo_run_desc *runs, const apo_batch_option
         }
         h->batch_view = true;
         // a batch fills the GPU with runs: fewer, fuller workgroups per run
-        // (above 32 dimensions the tiled step takes 8 lanes per protozoan
-        // with two or four chunks each, so a workgroup holds 64 rows)
-        if (h->dim > 32 && h->dim <= 128) h->p.lanes = 8;
+        // (rotated separable objectives: the tiled step takes 4 lanes per
+        // protozoan up to 64 dimensions and 8 up to 128, with up to four
+        // chunks each, 128 or 64 rows a workgroup -- their results do not
+        // depend on the lane count, since candidates are elementwise, masks
+        // are sets and the objective is summed from the matrix-core tiles
+        // in a fixed order; Rosenbrock's lane sums would change)
+        if (h->p.rotated && h->p.kind != apok::K_ROSENBROCK) {
+            if (h->dim > 16 && h->dim <= 64) h->p.lanes = 4;
+            else if (h->dim > 64 && h->dim <= 128) h->p.lanes = 8;
+        }
         h->p.rows = apok::tile_rows_wide(h->p.lanes ? h->p.lanes : apok::lanes_for_dim(h->dim));
         h->p.rank_lds = h->pop <= apok::kRankLdsMax ? 1 : 0;
         b->runs.push_back(h);

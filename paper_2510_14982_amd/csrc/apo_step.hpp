@@ -945,8 +945,8 @@ hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLa
     }
         APO_TILE(4, 1, 16) APO_TILE(8, 1, 16) APO_TILE(16, 1, 16) APO_TILE(32, 1, 16)
         APO_TILE(64, 1, 16) APO_TILE(64, 2, 16)
-        APO_TILE(4, 1, 128) APO_TILE(8, 1, 64) APO_TILE(16, 1, 32) APO_TILE(8, 2, 64)
-        APO_TILE(8, 4, 64)
+        APO_TILE(4, 1, 128) APO_TILE(8, 1, 64) APO_TILE(16, 1, 32) APO_TILE(4, 2, 128)
+        APO_TILE(4, 4, 128) APO_TILE(8, 4, 64)
 #undef APO_TILE
         return hipErrorInvalidValue;
     }

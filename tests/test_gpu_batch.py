@@ -23,6 +23,11 @@ def _mixed_runs(max_iter=40):
     runs = [_spec(w) for w in gen.batched_runs(n=9, seed=7, max_iter=max_iter,
                                                dims=(10, 20, 50, 100), pops=(64, 130),
                                                kinds=("rastrigin", "rosenbrock", "ackley"))]
+    # larger dimensions (the batch's own lane counts for separable objectives)
+    for seed, dim in ((11, 50), (12, 100)):
+        runs += [_spec(w) for w in gen.batched_runs(n=3, seed=seed, max_iter=max_iter,
+                                                    dims=(dim,), pops=(64, 130),
+                                                    kinds=("rastrigin", "rosenbrock", "ackley"))]
     w = gen.shifted_rastrigin_small(seed=3)
     runs.append(dict(_spec(w), max_iter=max_iter))
     img = gen.blob_image(128, 128, seed=2)
