@@ -76,7 +76,8 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
         L.Np = (dim + 127) / 128 * 128;
         const bool bf = o.precision == APO_BF16;
         L.gYr = take((size_t)pop * L.Dp * 4);
-        L.gAb = bf ? take((size_t)pop * L.Kp * 2) : 0;
+        // BF16 A in fragment order, whole 256-row tiles of the product
+        L.gAb = bf ? take((size_t)((pop + 255) / 256 * 256) * L.Kp * 2) : 0;
         L.gan = bf ? take((size_t)pop * 4) : 0;
         L.gP1 = take((size_t)pop * (L.Np / 64) * 4);
         L.gP2 = take((size_t)pop * (L.Np / 64) * 4);

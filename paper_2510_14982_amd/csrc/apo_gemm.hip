@@ -91,7 +91,9 @@ __global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init)
     }
     const T *o = (const T *)p.shift;
     float *yrow = w.Yr + (size_t)item * Dp;
-    uint16_t *arow = BF16 ? w.Ab + (size_t)item * w.Kp : nullptr;
+    // BF16 A in MFMA fragment order: block (item / 16, d / 32) holds 64 lanes
+    // x 8 values, lane item % 16 + 16 ((d % 32) / 8) taking d % 8 = 0..7
+    uint16_t *ablk = BF16 ? w.Ab + (size_t)(item >> 4) * (size_t)(w.Kp / 32) * 512 : nullptr;
     float ss = 0.f;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
@@ -102,11 +104,17 @@ __global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init)
                                  rw.ap[ch], rw.am[ch], rw.ap[ch], y);
             load4(o + d0, ov);
             store4(yrow + d0, y);
+            uint32_t hb[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float a = d0 + e < D ? y[e] - ov[e] : 0.f;
                 ss += a * a;
-                if (BF16) arow[d0 + e] = to_bf16(a);
+                hb[e] = BF16 ? to_bf16(a) : 0u;
+            }
+            if (BF16) {
+                const int kk = d0 & 31, lf = (item & 15) + 16 * (kk >> 3);
+                *(uint2 *)(ablk + ((size_t)(d0 >> 5) * 64 + lf) * 8 + (kk & 7)) =
+                    make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
             }
         }
     }
@@ -272,15 +280,17 @@ struct BChunkA {
     u32x4 v[4][kBKS];   // [row tile][k-step]: 8 BF16 of K per lane and step
 };
 
-// A of chunk kc (K elements) for the lane's four row tiles: byte offsets
-// aoff[i] from the uniform base, 16 bytes per k-step.
+// A of chunk kc (K elements) for the lane's four row tiles: A is stored in
+// fragment order (each 16-row x 32-K block is the 64 lanes' 16 bytes in lane
+// order), so a wavefront's load of one tile is 1 KiB contiguous; aoff[i] is
+// the lane's byte offset in its row group's first block.
 __device__ __forceinline__ void bf16_load_a(const unsigned char *abase, const uint32_t (&aoff)[4],
                                             int kc, BChunkA &a) {
-    const unsigned char *b = abase + (size_t)kc * 2;
+    const unsigned char *b = abase + (size_t)kc * 32;   // 1 KiB per 32 K
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int s = 0; s < kBKS; ++s) a.v[i][s] = *(const u32x4 *)(b + aoff[i] + 64 * s);
+        for (int s = 0; s < kBKS; ++s) a.v[i][s] = *(const u32x4 *)(b + aoff[i] + 1024 * s);
 }
 
 // Prefetch depths of the BF16 product, in chunks: A rows come from HBM (or
@@ -352,15 +362,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int m0 = rb * kBM, n0 = nb * kBN;
     if (m0 >= nrows) return;   // the whole workgroup: no barrier is skipped
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
-    // lane l: row 16 i + l % 16 of the wavefront's rows, K offset 8 (l / 16);
-    // rows past the end read the last row (their sums are not stored).  The
-    // 32-bit byte offsets hold: at most 65536 rows of 1024 BF16 values (128 MiB).
+    // lane l: row 16 i + l % 16 of the wavefront's rows, K offset 8 (l / 16),
+    // in the row group's fragment-order blocks (A holds whole 256-row tiles;
+    // rows past the end are zero and their sums are not stored).  The 32-bit
+    // byte offsets hold: at most 65536 rows of 1024 BF16 values (128 MiB).
     const unsigned char *abase = (const unsigned char *)g.Ab;
     uint32_t aoff[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int row = min(m0 + 64 * wave + 16 * i + (l & 15), nrows - 1);
-        aoff[i] = (uint32_t)row * (uint32_t)g.Kp * 2u + (uint32_t)(l >> 4) * 16u;
+        const uint32_t rg = (uint32_t)(m0 + 64 * wave + 16 * i) >> 4;
+        aoff[i] = (rg * (uint32_t)(g.Kp / 32) * 64u + (uint32_t)l) * 16u;
     }
     // M staging: thread tid moves 16-byte unit tid % kBU of rows
     // (256 / kBU) q + tid / kBU

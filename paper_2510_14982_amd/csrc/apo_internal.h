@@ -31,7 +31,8 @@ struct Ctrl {
 // the rescore list and M in the operand precisions.
 struct GemmBufs {
     float *Yr;            // [pop][Dp] candidates by rank
-    uint16_t *Ab;         // [pop][Kp] BF16 y - o (BF16 form)
+    uint16_t *Ab;         // BF16 y - o in MFMA fragment order (BF16 form): per 16-row
+                          // group and 32-K chunk, 64 lanes x 8 values (pop padded to 256)
     float *anorm;         // [pop] ||y - o||_2 (BF16 form)
     float *P1, *P2;       // [pop][Np / 64] partial row sums
     int32_t *list;        // [pop] ranks to re-score in binary32
