@@ -635,14 +635,21 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         std::memcpy(gmd.data(), M, (size_t)dim * dim * 8);
         if (opt->objective.shift) std::memcpy(go.data(), opt->objective.shift, (size_t)dim * 8);
         if (p.gb.bf16) {
+            // BF16 M in MFMA fragment order: per 16-row group n / 16 and 32-K
+            // chunk k / 32 a block of 64 lanes x 8 values, lane n % 16 +
+            // 16 ((k % 32) / 8) holding k % 8 = 0..7
             gmb.assign((size_t)L.Np * L.Kp * 2, 0);
             uint16_t *mb = reinterpret_cast<uint16_t *>(gmb.data());
-            for (size_t i = 0; i < (size_t)L.Np * L.Kp; ++i) {
-                uint32_t u;
-                std::memcpy(&u, &mf[i], 4);
-                u += 0x7FFFu + ((u >> 16) & 1u);   // finite entries of an orthogonal M
-                mb[i] = (uint16_t)(u >> 16);
-            }
+            const size_t kch = (size_t)L.Kp / 32;
+            for (size_t n = 0; n < (size_t)L.Np; ++n)
+                for (size_t k = 0; k < (size_t)L.Kp; ++k) {
+                    uint32_t u;
+                    std::memcpy(&u, &mf[n * L.Kp + k], 4);
+                    u += 0x7FFFu + ((u >> 16) & 1u);   // finite entries of an orthogonal M
+                    const size_t lane = (n & 15) + 16 * ((k & 31) >> 3);
+                    mb[(((n >> 4) * kch + (k >> 5)) * 64 + lane) * 8 + (k & 7)] =
+                        (uint16_t)(u >> 16);
+                }
         }
     }
     if (p.rotated && !gf) {

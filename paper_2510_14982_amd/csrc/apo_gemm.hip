@@ -25,13 +25,16 @@ constexpr size_t kGemmLds = 2 * (size_t)kGM * kGLds;   // dynamic LDS of the pro
 
 // BF16 product: 256 x 128 output tile per workgroup (4 wavefronts of 64 rows),
 // A straight from global memory into fragments, M's 128 rows through LDS in
-// chunks of kBK K, two buffers.
+// chunks of kBK K, two buffers.  Both BF16 operands are stored in MFMA
+// fragment order: per 16-row group and 32-K chunk one 1 KiB block, lane l's
+// 16 bytes holding row l % 16, K 8 (l / 16) .. + 7 of the chunk.
 constexpr int kBM = 256, kBN = 128, kBK = 32;
 constexpr int kBKS = kBK / 32;           // MFMA k-steps per chunk
-constexpr int kBU = kBK / 8;             // 16-byte units per row and chunk
-constexpr int kBQ = kBN * kBU / 256;     // units each thread stages per chunk
-constexpr int kBLds = 2 * kBK + 16;      // LDS row stride in bytes (odd number of units)
-constexpr size_t kBLdsBytes = 2 * (size_t)kBN * kBLds;
+static_assert(kBK == 32, "one fragment block of M per chunk");
+constexpr int kBQ = 2;                   // 16-byte units each thread stages per chunk
+constexpr int kBBlk = 1024;              // bytes of one fragment block
+constexpr size_t kBBuf = (size_t)(kBN / 16) * kBBlk;   // M of one chunk: 8 blocks
+constexpr size_t kBLdsBytes = 2 * kBBuf;
 // LDS reserved at launch: more than half of a CU's 160 KB, so that a CU
 // holds one workgroup and a grid of one workgroup per CU spreads over all CUs.
 constexpr size_t kBLdsLaunch = 96 * 1024;
@@ -306,27 +309,25 @@ constexpr int kBDA = 3, kBDB = 2;
 template <int PH>
 __device__ __forceinline__ void bf16_chunk(int c, int nc, const unsigned char *abase,
                                            const uint32_t (&aoff)[4],
-                                           const unsigned char *bsrc, size_t rstride,
+                                           const unsigned char *bsrc, size_t bstride,
                                            unsigned char *bdst, const unsigned char *bfr,
                                            BChunkA (&a)[4], u32x4 (&bs)[2][kBQ],
                                            f32x4 (&acc)[4][8]) {
     {
-        const int cb = min(c + kBDB, nc - 1);
+        const size_t ob = (size_t)min(c + kBDB, nc - 1) * kBBlk;
 #pragma unroll
-        for (int q = 0; q < kBQ; ++q)
-            bs[PH % 2][q] =
-                *(const u32x4 *)(bsrc + (256 / kBU) * q * rstride + (size_t)cb * (kBK * 2));
+        for (int q = 0; q < kBQ; ++q) bs[PH % 2][q] = *(const u32x4 *)(bsrc + q * bstride + ob);
         bf16_load_a(abase, aoff, min(c + kBDA, nc - 1) * kBK, a[(PH + kBDA) % 4]);
     }
     __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the MFMA work
     const BChunkA &cur = a[PH];
-    const unsigned char *sb = bfr + (PH & 1) * (kBN * kBLds);
+    const unsigned char *sb = bfr + (PH & 1) * kBBuf;
 #pragma unroll
     for (int s = 0; s < kBKS; ++s) {
-        // lane l: B[k = 32 s + 8 (l / 16) .. + 7][column 16 j + l % 16]
+        // lane l: B[k = 8 (l / 16) .. + 7 of the chunk][column 16 j + l % 16]
         u32x4 bv[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bv[j] = *(const u32x4 *)(sb + 16 * j * kBLds + 64 * s);
+        for (int j = 0; j < 8; ++j) bv[j] = *(const u32x4 *)(sb + j * kBBlk);
         __builtin_amdgcn_sched_barrier(0);   // all eight reads in flight before the MFMAs
 #pragma unroll
         for (int j = 0; j < 8; ++j)
@@ -337,9 +338,9 @@ __device__ __forceinline__ void bf16_chunk(int c, int nc, const unsigned char *a
                     acc[i][j], 0, 0, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
-    unsigned char *d = bdst + ((PH + 1) & 1) * (kBN * kBLds);
+    unsigned char *d = bdst + ((PH + 1) & 1) * kBBuf;
 #pragma unroll
-    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(d + (256 / kBU) * q * kBLds) = bs[(PH + 1) % 2][q];
+    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(d + q * (4 * kBBlk)) = bs[(PH + 1) % 2][q];
     __syncthreads();
 }
 
@@ -373,14 +374,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         const uint32_t rg = (uint32_t)(m0 + 64 * wave + 16 * i) >> 4;
         aoff[i] = (rg * (uint32_t)(g.Kp / 32) * 64u + (uint32_t)l) * 16u;
     }
-    // M staging: thread tid moves 16-byte unit tid % kBU of rows
-    // (256 / kBU) q + tid / kBU
-    const size_t rstride = (size_t)g.Kp * 2;
-    const unsigned char *bsrc =
-        (const unsigned char *)g.B + (size_t)(n0 + tid / kBU) * rstride + (tid % kBU) * 16;
-    unsigned char *bdst = gsm + (tid / kBU) * kBLds + (tid % kBU) * 16;
-    // fragment reads: lane l reads row 16 j + l % 16 of the chunk at K 8 (l / 16)
-    const unsigned char *bfr = gsm + (l & 15) * kBLds + (l >> 4) * 16;
+    // M staging: thread tid moves lane tid % 64 of column groups n0 / 16 +
+    // tid / 64 + 4 q (fragment blocks, contiguous per wavefront), to the same
+    // place of the chunk's LDS buffer
+    const size_t bstride = (size_t)4 * (g.Kp / 32) * kBBlk;   // four column groups on
+    const unsigned char *bsrc = (const unsigned char *)g.B +
+                                ((size_t)(n0 / 16 + (tid >> 6)) * (g.Kp / 32) * kBBlk) +
+                                (size_t)(tid & 63) * 16;
+    unsigned char *bdst = gsm + (tid >> 6) * kBBlk + (tid & 63) * 16;
+    // fragment reads: lane l's 16 bytes of column group j's block
+    const unsigned char *bfr = gsm + l * 16;
     f32x4 acc[4][8];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -393,19 +396,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // M of chunk 1 into bs[1]
 #pragma unroll
     for (int q = 0; q < kBQ; ++q) {
-        bs[0][q] = *(const u32x4 *)(bsrc + (256 / kBU) * q * rstride);
-        bs[1][q] = *(const u32x4 *)(bsrc + (256 / kBU) * q * rstride + (size_t)kBK * 2);
+        bs[0][q] = *(const u32x4 *)(bsrc + q * bstride);
+        bs[1][q] = *(const u32x4 *)(bsrc + q * bstride + kBBlk);
     }
 #pragma unroll
     for (int c = 0; c < kBDA; ++c) bf16_load_a(abase, aoff, c * kBK, a[c]);
 #pragma unroll
-    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(bdst + (256 / kBU) * q * kBLds) = bs[0][q];
+    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(bdst + q * (4 * kBBlk)) = bs[0][q];
     __syncthreads();
     for (int c = 0; c < nc; c += 4) {
-        bf16_chunk<0>(c, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
-        bf16_chunk<1>(c + 1, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
-        bf16_chunk<2>(c + 2, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
-        bf16_chunk<3>(c + 3, nc, abase, aoff, bsrc, rstride, bdst, bfr, a, bs, acc);
+        bf16_chunk<0>(c, nc, abase, aoff, bsrc, bstride, bdst, bfr, a, bs, acc);
+        bf16_chunk<1>(c + 1, nc, abase, aoff, bsrc, bstride, bdst, bfr, a, bs, acc);
+        bf16_chunk<2>(c + 2, nc, abase, aoff, bsrc, bstride, bdst, bfr, a, bs, acc);
+        bf16_chunk<3>(c + 3, nc, abase, aoff, bsrc, bstride, bdst, bfr, a, bs, acc);
     }
     // epilogue: element v of lane l in tile (i, j) is Z[row 4 (l / 16) + v][col l % 16];
     // columns 0..63 and 64..127 of the tile give two half partials

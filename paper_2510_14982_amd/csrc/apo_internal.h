@@ -39,7 +39,7 @@ struct GemmBufs {
     int32_t *status;      // [pop] rank's slot in the list, or -1 (settled rejection)
     int32_t *count;       // its length
     unsigned long long *total;   // rows re-scored so far (BF16 form)
-    const uint16_t *Mb;   // [Np][Kp] M in BF16
+    const uint16_t *Mb;   // M in BF16, MFMA fragment order (1 KiB per 16 rows x 32 K)
     const float *Mf;      // [Np][Kp] M in binary32
     const double *Md;     // [dim][dim] M in binary64 (elite re-score)
     const double *o64;    // [dim] shift in binary64
