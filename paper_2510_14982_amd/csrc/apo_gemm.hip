@@ -14,14 +14,17 @@
 
 namespace apok {
 
-// Binary32 product: 128 x 128 output tile per workgroup, both operands staged
+// Binary32 product: 128 x 64 output tile per workgroup, both operands staged
 // through LDS in chunks of 32 K.
-constexpr int kGM = 128, kGN = 128;      // output tile of a workgroup
+constexpr int kGM = 128, kGN = 64;       // output tile of a workgroup
+static_assert(kGN == 64, "a workgroup sums one 64-column objective half");
 constexpr int kGRowB = 128;              // bytes of K per row and chunk
 constexpr int kGLds = kGRowB + 16;       // LDS row stride in bytes (9 x 16: rows of a
                                          // fragment read fall in distinct bank groups)
-constexpr int kGQ = kGRowB / 32;         // 16-byte vectors per loader thread and matrix
-constexpr size_t kGemmLds = 2 * (size_t)kGM * kGLds;   // dynamic LDS of the product
+constexpr int kGQ = kGRowB / 32;         // 16-byte vectors of A per loader thread
+constexpr int kGBT = 256 / kGN;          // loader threads per row of M
+constexpr int kGQB = kGRowB / kGBT / 16; // 16-byte vectors of M per loader thread
+constexpr size_t kGemmLds = (size_t)(kGM + kGN) * kGLds;   // dynamic LDS of the product
 
 // BF16 product: 256 x 128 output tile per workgroup (4 wavefronts of 64 rows),
 // A straight from global memory into fragments, M's 128 rows through LDS in
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init)
 // into registers: B from the packed binary32 M rows, A = y - o computed from
 // the binary32 candidates.
 struct GemmChunk {
-    uint4 a[kGQ], b[kGQ];
+    uint4 a[kGQ], b[kGQB];
 };
 
 __device__ __forceinline__ GemmChunk gemm_fetch(const GemmRun &g, const unsigned char *Bp,
@@ -140,7 +143,7 @@ __device__ __forceinline__ GemmChunk gemm_fetch(const GemmRun &g, const unsigned
     GemmChunk c;
     const uint4 *bp = (const uint4 *)(Bp + (size_t)kc * 4);
 #pragma unroll
-    for (int q = 0; q < kGQ; ++q) c.b[q] = bp[q];
+    for (int q = 0; q < kGQB; ++q) c.b[q] = bp[q];
     const int k0 = kc + lh * (kGRowB / 8);   // 4-byte elements of the half row
     const float *yr = g.Yr + (size_t)arow * g.Dp;
     if (live && k0 + 4 * kGQ <= g.D) {
@@ -189,8 +192,9 @@ __device__ __forceinline__ void obj_terms(float z, bool live, float &g1, float &
 // Binary32 product Z = A M^T with the objective's per-row sums over each
 // 64-column half tile fused into the epilogue.  Rows are list slots (the
 // ranks of a re-score list) or ranks; A = y - o is computed from Yr while
-// loading.  Workgroup: 4 wavefronts, each a 64 x 64 quadrant of 4 x 4 MFMA
-// 16 x 16 x 4 tiles; K in chunks of 128 bytes per row, the next chunk
+// loading.  Workgroup: 128 rows x 64 columns (one objective half), 4
+// wavefronts of 32 rows each (2 x 4 MFMA 16 x 16 x 4 tiles), so that a CU
+// holds four workgroups; K in chunks of 128 bytes per row, the next chunk
 // fetched into registers during the MFMA work.
 // ---------------------------------------------------------------------------
 template <int KIND>
@@ -203,28 +207,28 @@ __global__ __launch_bounds__(256) void gemm_obj_f32(GemmRun g) {
     if (m0 >= nrows) return;   // the whole workgroup: no barrier is skipped
     const int n0 = blockIdx.x * kGN;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
-    const int lr = tid >> 1, lh = tid & 1;                  // loader: row, half chunk
+    const int lr = tid >> 1, lh = tid & 1;                  // A loader: row, half chunk
+    const int br = tid / kGBT, bq = tid % kGBT;              // M loader: row, part
     const int slot = m0 + lr;
     const bool live = slot < nrows;
     const int arow = live ? (g.list ? g.list[slot] : slot) : 0;
     const unsigned char *Bp =
-        (const unsigned char *)g.B + (size_t)(n0 + lr) * g.Kp * 4 + lh * (kGRowB / 2);
-    f32x4 acc[4][4];
+        (const unsigned char *)g.B + (size_t)(n0 + br) * g.Kp * 4 + bq * (kGQB * 16);
+    f32x4 acc[2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int wr = 64 * (wave >> 1), wc = 64 * (wave & 1);
+    const int wr = 32 * wave;
     GemmChunk ch = gemm_fetch(g, Bp, arow, live, lh, 0);
     for (int kc = 0; kc < g.Kp; kc += KC) {
         __syncthreads();   // the previous chunk's readers are done
         uint4 *da = (uint4 *)(sA + lr * kGLds + lh * (kGRowB / 2));
-        uint4 *db = (uint4 *)(sB + lr * kGLds + lh * (kGRowB / 2));
+        uint4 *db = (uint4 *)(sB + br * kGLds + bq * (kGQB * 16));
 #pragma unroll
-        for (int q = 0; q < kGQ; ++q) {
-            da[q] = ch.a[q];
-            db[q] = ch.b[q];
-        }
+        for (int q = 0; q < kGQ; ++q) da[q] = ch.a[q];
+#pragma unroll
+        for (int q = 0; q < kGQB; ++q) db[q] = ch.b[q];
         __syncthreads();
         if (kc + KC < g.Kp)   // in flight during the MFMA work
             ch = gemm_fetch(g, Bp, arow, live, lh, kc + KC);
@@ -232,29 +236,30 @@ __global__ __launch_bounds__(256) void gemm_obj_f32(GemmRun g) {
         for (int ks = 0; ks < KC / 4; ++ks) {
             // 16 x 16 x 4 FP32: lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
             const int kb = (ks * 4 + (l >> 4)) * 4;
-            float a[4], b[4];
+            float a[2], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < 2; ++i)
                 a[i] = *(const float *)(sA + (wr + 16 * i + (l & 15)) * kGLds + kb);
-                b[i] = *(const float *)(sB + (wc + 16 * i + (l & 15)) * kGLds + kb);
-            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                b[j] = *(const float *)(sB + (16 * j + (l & 15)) * kGLds + kb);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
     // epilogue: element v of lane l in tile (i, j) is Z[row 4 (l / 16) + v][col l % 16]
-    const int half = (n0 + wc) / 64, NH = g.Np / 64;
+    const int half = n0 / 64, NH = g.Np / 64;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             float g1 = 0.f, g2 = 0.f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int col = n0 + wc + 16 * j + (l & 15);
+                const int col = n0 + 16 * j + (l & 15);
                 obj_terms<KIND>(acc[i][j][v], col < g.D, g1, g2);
             }
             g1 = group_sum<16>(g1);
