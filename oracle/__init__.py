@@ -43,35 +43,56 @@ class _Trace(C.Structure):
 _lib = None
 
 
+class _Draws(C.Structure):
+    """One rank's draws for ``oracle_step_scripted`` (``oracle_draws``)."""
+    _fields_ = [
+        ("in_dr", C.c_int32), ("u_op", C.c_double), ("u_f", C.c_double), ("u_rep", C.c_double),
+        ("sgn", C.c_double), ("j", C.c_int32), ("km", C.c_int32 * 8), ("kp", C.c_int32 * 8),
+        ("mask", C.POINTER(C.c_uint8)), ("U", C.POINTER(C.c_double)),
+    ]
+
+
+def _configure(L):
+    P = C.POINTER
+    L.oracle_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+    L.oracle_uniform.restype = C.c_double
+    L.oracle_uniform.argtypes = [C.c_uint32]
+    L.oracle_bounded.restype = C.c_uint32
+    L.oracle_bounded.argtypes = [C.c_uint32, C.c_uint32]
+    L.oracle_subset_pi.restype = C.c_uint32
+    L.oracle_subset_pi.argtypes = [C.c_uint32, C.c_uint32, P(C.c_uint32)]
+    L.oracle_subset_mask.argtypes = [C.c_uint32, C.c_uint32, P(C.c_uint32), P(C.c_uint8)]
+    L.oracle_objective.restype = C.c_double
+    L.oracle_objective.argtypes = [P(_Problem), P(C.c_double)]
+    L.oracle_rank_order.argtypes = [C.c_int32, P(C.c_double), P(C.c_int32)]
+    L.oracle_init.argtypes = [P(_Problem), P(C.c_double), P(C.c_double)]
+    L.oracle_finish.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_double),
+                                P(C.c_double), P(C.c_uint8)]
+    L.oracle_step.restype = C.c_int
+    L.oracle_step.argtypes = [P(_Problem), C.c_int32, P(C.c_double), P(C.c_double), P(_Trace)]
+    L.oracle_step_scripted.restype = C.c_int
+    L.oracle_step_scripted.argtypes = [P(_Problem), C.c_int32, P(C.c_double), P(C.c_double),
+                                       P(_Draws), P(_Trace)]
+    L.oracle_best.restype = C.c_int32
+    L.oracle_best.argtypes = [C.c_int32, P(C.c_double)]
+    L.oracle_run.restype = C.c_int32
+    L.oracle_run.argtypes = [P(_Problem), C.c_int32, C.c_int32, P(C.c_double), P(C.c_double)]
+    L.oracle_histogram_u8.argtypes = [P(C.c_uint8), C.c_uint64, P(C.c_uint64)]
+    return L
+
+
+def load(path: str):
+    """A separately built copy of the oracle (used by the tests that check
+    the pins reject deliberately altered copies of the oracle source)."""
+    return _configure(C.CDLL(path))
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_build.LIB):
             _build.build()
-        L = C.CDLL(_build.LIB)
-        P = C.POINTER
-        L.oracle_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
-        L.oracle_uniform.restype = C.c_double
-        L.oracle_uniform.argtypes = [C.c_uint32]
-        L.oracle_bounded.restype = C.c_uint32
-        L.oracle_bounded.argtypes = [C.c_uint32, C.c_uint32]
-        L.oracle_subset_pi.restype = C.c_uint32
-        L.oracle_subset_pi.argtypes = [C.c_uint32, C.c_uint32, P(C.c_uint32)]
-        L.oracle_subset_mask.argtypes = [C.c_uint32, C.c_uint32, P(C.c_uint32), P(C.c_uint8)]
-        L.oracle_objective.restype = C.c_double
-        L.oracle_objective.argtypes = [P(_Problem), P(C.c_double)]
-        L.oracle_rank_order.argtypes = [C.c_int32, P(C.c_double), P(C.c_int32)]
-        L.oracle_init.argtypes = [P(_Problem), P(C.c_double), P(C.c_double)]
-        L.oracle_finish.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_double),
-                                    P(C.c_double), P(C.c_uint8)]
-        L.oracle_step.restype = C.c_int
-        L.oracle_step.argtypes = [P(_Problem), C.c_int32, P(C.c_double), P(C.c_double), P(_Trace)]
-        L.oracle_best.restype = C.c_int32
-        L.oracle_best.argtypes = [C.c_int32, P(C.c_double)]
-        L.oracle_run.restype = C.c_int32
-        L.oracle_run.argtypes = [P(_Problem), C.c_int32, C.c_int32, P(C.c_double), P(C.c_double)]
-        L.oracle_histogram_u8.argtypes = [P(C.c_uint8), C.c_uint64, P(C.c_uint64)]
-        _lib = L
+        _lib = _configure(C.CDLL(_build.LIB))
     return _lib
 
 
@@ -160,6 +181,7 @@ class Problem:
     rot: Optional[np.ndarray] = None
     hist: Optional[np.ndarray] = None
     pdr_plus: bool = False          # Eq. (13) with the opposite sign (a variant)
+    lib: object = field(default=None, repr=False)   # None: the built oracle
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -177,6 +199,9 @@ class Problem:
             if self.lb.min() < 0 or self.ub.max() > 255:
                 raise ValueError("threshold bounds must lie in [0, 255]")
 
+    def _lib(self):
+        return self.lib if self.lib is not None else lib()
+
     def _c(self) -> _Problem:
         s = _Problem()
         s.dim, s.pop, s.np, s.max_iter = self.dim, self.pop, self.np_pairs, self.max_iter
@@ -192,13 +217,13 @@ class Problem:
     def objective(self, x) -> float:
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.dim)
         s = self._c()
-        return lib().oracle_objective(C.byref(s), _ptr(x, C.c_double))
+        return self._lib().oracle_objective(C.byref(s), _ptr(x, C.c_double))
 
     def init(self):
         X = np.zeros((self.pop, self.dim))
         F = np.zeros(self.pop)
         s = self._c()
-        lib().oracle_init(C.byref(s), _ptr(X, C.c_double), _ptr(F, C.c_double))
+        self._lib().oracle_init(C.byref(s), _ptr(X, C.c_double), _ptr(F, C.c_double))
         return X, F
 
     def finish(self, X, F, Y):
@@ -209,31 +234,35 @@ class Problem:
         Fy = np.zeros(self.pop)
         acc = np.zeros(self.pop, dtype=np.uint8)
         s = self._c()
-        lib().oracle_finish(C.byref(s), _ptr(X, C.c_double), _ptr(F, C.c_double),
+        self._lib().oracle_finish(C.byref(s), _ptr(X, C.c_double), _ptr(F, C.c_double),
                             _ptr(Y, C.c_double), _ptr(Fy, C.c_double), _ptr(acc, C.c_uint8))
         return X, F, Y, Fy, acc.astype(bool)
+
+    def _trace(self):
+        nbw = 1 + 2 * self.np_pairs
+        tr = StepTrace(Y=np.zeros((self.pop, self.dim)), Fy=np.zeros(self.pop),
+                       op=np.zeros(self.pop, np.int32), perm=np.zeros(self.pop, np.int32),
+                       mcount=np.zeros(self.pop, np.int32),
+                       nb=np.zeros((self.pop, nbw), np.int32),
+                       accepted=np.zeros(self.pop, np.uint8), dr_count=0)
+        drc = np.zeros(1, np.int32)
+        c_tr = _Trace(_ptr(tr.Y, C.c_double), _ptr(tr.Fy, C.c_double),
+                      _ptr(tr.op, C.c_int32), _ptr(tr.perm, C.c_int32),
+                      _ptr(tr.mcount, C.c_int32), _ptr(tr.nb, C.c_int32),
+                      _ptr(tr.accepted, C.c_uint8), _ptr(drc, C.c_int32))
+        return tr, c_tr, drc
 
     def step(self, t, X, F, trace: bool = True):
         """Iteration t (1-based) from state (X, F); returns (X', F', trace)."""
         X = np.array(X, dtype=np.float64, order="C")
         F = np.array(F, dtype=np.float64)
-        tr = None
-        c_tr = None
+        tr = c_tr = drc = None
         if trace:
-            nbw = 1 + 2 * self.np_pairs
-            tr = StepTrace(Y=np.zeros((self.pop, self.dim)), Fy=np.zeros(self.pop),
-                           op=np.zeros(self.pop, np.int32), perm=np.zeros(self.pop, np.int32),
-                           mcount=np.zeros(self.pop, np.int32),
-                           nb=np.zeros((self.pop, nbw), np.int32),
-                           accepted=np.zeros(self.pop, np.uint8), dr_count=0)
-            drc = np.zeros(1, np.int32)
-            c_tr = _Trace(_ptr(tr.Y, C.c_double), _ptr(tr.Fy, C.c_double),
-                          _ptr(tr.op, C.c_int32), _ptr(tr.perm, C.c_int32),
-                          _ptr(tr.mcount, C.c_int32), _ptr(tr.nb, C.c_int32),
-                          _ptr(tr.accepted, C.c_uint8), _ptr(drc, C.c_int32))
+            tr, c_tr, drc = self._trace()
         s = self._c()
-        rc = lib().oracle_step(C.byref(s), int(t), _ptr(X, C.c_double), _ptr(F, C.c_double),
-                               C.byref(c_tr) if c_tr is not None else None)
+        rc = self._lib().oracle_step(C.byref(s), int(t), _ptr(X, C.c_double),
+                                     _ptr(F, C.c_double),
+                                     C.byref(c_tr) if c_tr is not None else None)
         if rc != 0:
             raise ValueError(f"oracle_step rejected t={t}")
         if tr is not None:
@@ -241,11 +270,51 @@ class Problem:
             tr.accepted = tr.accepted.astype(bool)
         return X, F, tr
 
+    def step_scripted(self, t, X, F, draws):
+        """Iteration t with every random value supplied instead of drawn.
+
+        ``draws[r]`` (r = 0-based rank after the sort) is a dict with keys
+        in_dr (bool), u_op, u_f, u_rep, sgn (+1 / -1), j, km, kp (lists of
+        np ranks), mask (D zeros / ones) and U (D values in (0, 1)); missing
+        keys default to 0 (empty mask).  Returns (X', F', trace)."""
+        if len(draws) != self.pop:
+            raise ValueError("one draw record per rank")
+        X = np.array(X, dtype=np.float64, order="C")
+        F = np.array(F, dtype=np.float64)
+        recs = (_Draws * self.pop)()
+        keep = []
+        for r, d in enumerate(draws):
+            c = recs[r]
+            c.in_dr = 1 if d.get("in_dr", False) else 0
+            c.u_op, c.u_f = float(d.get("u_op", 0.0)), float(d.get("u_f", 0.0))
+            c.u_rep, c.sgn = float(d.get("u_rep", 0.0)), float(d.get("sgn", 1.0))
+            c.j = int(d.get("j", 0))
+            for k, v in enumerate(d.get("km", [])):
+                c.km[k] = int(v)
+            for k, v in enumerate(d.get("kp", [])):
+                c.kp[k] = int(v)
+            m = np.ascontiguousarray(d.get("mask", np.zeros(self.dim)), dtype=np.uint8)
+            u = np.ascontiguousarray(d.get("U", np.zeros(self.dim)), dtype=np.float64)
+            if m.shape != (self.dim,) or u.shape != (self.dim,):
+                raise ValueError("mask and U hold one value per coordinate")
+            keep += [m, u]
+            c.mask = _ptr(m, C.c_uint8)
+            c.U = _ptr(u, C.c_double)
+        tr, c_tr, drc = self._trace()
+        s = self._c()
+        rc = self._lib().oracle_step_scripted(C.byref(s), int(t), _ptr(X, C.c_double),
+                                              _ptr(F, C.c_double), recs, C.byref(c_tr))
+        if rc != 0:
+            raise ValueError(f"oracle_step_scripted rejected t={t}")
+        tr.dr_count = int(drc[0])
+        tr.accepted = tr.accepted.astype(bool)
+        return X, F, tr
+
     def run(self, X, F, t0: int, iters: int):
         X = np.array(X, dtype=np.float64, order="C")
         F = np.array(F, dtype=np.float64)
         s = self._c()
-        t = lib().oracle_run(C.byref(s), int(t0), int(iters), _ptr(X, C.c_double),
+        t = self._lib().oracle_run(C.byref(s), int(t0), int(iters), _ptr(X, C.c_double),
                              _ptr(F, C.c_double))
         return X, F, int(t)
 

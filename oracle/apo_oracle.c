@@ -466,16 +466,198 @@ OR_EXPORT void oracle_finish(const oracle_problem *p, double *X, double *F, doub
 }
 
 /* ------------------------------------------------------------------ */
-/* One iteration t (1-based) of Algorithm 1, synchronous: every         */
-/* candidate is built from the population as it stood when the          */
-/* iteration began.                                                     */
+/* The random values one rank consumes in one iteration.  oracle_step   */
+/* draws them from the Philox stream; oracle_step_scripted takes them   */
+/* from the caller, so hand-worked cases can fix every draw and check   */
+/* the update formulas value by value.                                  */
 /* ------------------------------------------------------------------ */
-OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double *F,
-                          oracle_trace *tr)
+#define OR_MAX_NP 8
+
+typedef struct {
+    int32_t in_dr;            /* the rank belongs to Dr (Algorithm 1)             */
+    double u_op;              /* rand compared with p_dr (Eq. (13)) or p_ah (Eq. (12)) */
+    double u_f;               /* rand of the foraging factor, Eq. (4)             */
+    double u_rep;             /* rand of Eq. (2)                                  */
+    double sgn;               /* the "+-" of Eqs. (2) and (9): +1 or -1           */
+    int32_t j;                /* rank of X_j, Eq. (6)                             */
+    int32_t km[OR_MAX_NP];    /* ranks k- of the pairs of Eq. (6)                 */
+    int32_t kp[OR_MAX_NP];    /* ranks k+ of the pairs of Eq. (6)                 */
+    const uint8_t *mask;      /* [dim] M_r of Eq. (3) or M_f of Eq. (5), 1 = in   */
+    const double *U;          /* [dim] "Rand" of Eqs. (1), (2), (9)               */
+} oracle_draws;
+
+/* Which operation rank r (0-based; the paper's i = r + 1) performs in
+ * iteration t: in Dr, dormancy when p_dr of Eq. (13) exceeds rand, else
+ * reproduction; outside Dr, the autotrophic mode when p_ah of Eq. (12)
+ * exceeds rand, else the heterotrophic mode. */
+static int decide_op(const oracle_problem *p, int32_t t, int r, const oracle_draws *dw)
+{
+    const int ps = p->pop, i = r + 1, T = p->max_iter;
+    if (dw->in_dr) {
+        /* Eq. (13) as printed; the variant flips the sign in front of the
+         * cosine (the reading that makes the worst ranks, not the best,
+         * the likeliest to go dormant) */
+        double c_dr = cos((1.0 - (double)i / (double)ps) * OR_PI);
+        double p_dr = p->pdr_plus ? 0.5 * (1.0 + c_dr) : 0.5 * (1.0 - c_dr);
+        return p_dr > dw->u_op ? OR_DORMANCY : OR_REPRODUCTION;
+    }
+    double p_ah = 0.5 * (1.0 + cos(((double)t / (double)T) * OR_PI));
+    return p_ah > dw->u_op ? OR_AUTOTROPH : OR_HETEROTROPH;
+}
+
+/* The candidate of rank r for operation op (Eqs. (1), (2), (4), (6)-(10)),
+ * before the bound clamp, from the population (X, F by id) as it stood
+ * when the iteration began.  acc is [dim] scratch; nbrow (may be NULL)
+ * receives the neighbour ranks. */
+static void candidate(const oracle_problem *p, int32_t t, int r, int op, const int32_t *perm,
+                      const double *X, const double *F, const oracle_draws *dw, double *acc,
+                      double *y, int32_t *nbrow)
 {
     const int D = p->dim, ps = p->pop, np = p->np, T = p->max_iter;
     const double eps = 2.220446049250313e-16;   /* 2^-52 */
-    if (t < 1 || t > T)
+    const double *xi = &X[(size_t)perm[r] * D];
+    const double *U = dw->U;
+    const uint8_t *mask = dw->mask;
+
+    if (op == OR_DORMANCY) {
+        /* Eq. (1): a fresh protozoan in the bounds */
+        for (int d = 0; d < D; ++d)
+            y[d] = p->lb[d] + U[d] * (p->ub[d] - p->lb[d]);
+        return;
+    }
+    if (op == OR_REPRODUCTION) {
+        /* Eq. (2): X_i +- rand (X_min + Rand (X_max - X_min)) on M_r */
+        for (int d = 0; d < D; ++d) {
+            if (mask[d]) {
+                double R = p->lb[d] + U[d] * (p->ub[d] - p->lb[d]);
+                y[d] = xi[d] + (dw->sgn * dw->u_rep) * R;
+            } else {
+                y[d] = xi[d];
+            }
+        }
+        return;
+    }
+    /* foraging: the factor f of Eq. (4) */
+    const double f_scale = 1.0 + cos(((double)t / (double)T) * OR_PI);
+    const double fac = dw->u_f * f_scale;
+    for (int d = 0; d < D; ++d)
+        acc[d] = 0.0;
+    if (op == OR_AUTOTROPH) {
+        /* Eqs. (6), (7).  j is any rank; k- a strictly better rank (itself
+         * for the best); k+ a strictly worse rank (itself for the worst). */
+        if (nbrow)
+            nbrow[0] = dw->j;
+        for (int k = 1; k <= np; ++k) {
+            const int km = dw->km[k - 1], kp = dw->kp[k - 1];
+            if (nbrow) {
+                nbrow[2 * k - 1] = km;
+                nbrow[2 * k] = kp;
+            }
+            const int idm = perm[km], idp = perm[kp];
+            double wa = exp(-fabs(F[idm] / (F[idp] + eps)));
+            for (int d = 0; d < D; ++d)
+                acc[d] = acc[d] + wa * (X[(size_t)idm * D + d] - X[(size_t)idp * D + d]);
+        }
+        const double *xj = &X[(size_t)perm[dw->j] * D];
+        for (int d = 0; d < D; ++d) {
+            if (mask[d])
+                y[d] = xi[d] + fac * ((xj[d] - xi[d]) + acc[d] / (double)np);
+            else
+                y[d] = xi[d];
+        }
+        return;
+    }
+    /* heterotroph, Eqs. (8)-(10); ranks i-k and i+k are held inside
+     * [1, ps] */
+    const double near_scale = 1.0 - (double)t / (double)T;
+    for (int k = 1; k <= np; ++k) {
+        int a = r - k < 0 ? 0 : r - k;
+        int b = r + k > ps - 1 ? ps - 1 : r + k;
+        if (nbrow) {
+            nbrow[2 * k - 1] = a;
+            nbrow[2 * k] = b;
+        }
+        const int ida = perm[a], idb = perm[b];
+        double wh = exp(-fabs(F[ida] / (F[idb] + eps)));
+        for (int d = 0; d < D; ++d)
+            acc[d] = acc[d] + wh * (X[(size_t)ida * D + d] - X[(size_t)idb * D + d]);
+    }
+    for (int d = 0; d < D; ++d) {
+        if (mask[d]) {
+            double xnear = (1.0 + (dw->sgn * U[d]) * near_scale) * xi[d];   /* Eq. (9) */
+            y[d] = xi[d] + fac * ((xnear - xi[d]) + acc[d] / (double)np);
+        } else {
+            y[d] = xi[d];
+        }
+    }
+}
+
+/* Rank r's draws of iteration t from the Philox stream.  The scalars come
+ * first, then the operation is decided, and only then the mask, whose
+ * size depends on it: ceil(D rand) for reproduction (Eq. (3)), ceil(D i /
+ * ps) for foraging (Eq. (5)).  mask and U are [dim] buffers owned by the
+ * caller; returns the operation and the mask size. */
+static int philox_draws(const oracle_problem *p, int32_t t, int r, int m_dr,
+                        const uint32_t dr_keys[8], oracle_draws *dw, uint8_t *mask, double *U,
+                        int *m_out)
+{
+    const int D = p->dim, ps = p->pop, np = p->np, i = r + 1;
+    uint32_t s0[4], mkeys[8];
+    draw_block(p, TAG_RANK, 0, (uint32_t)r, (uint32_t)t, s0);
+    draw_block(p, TAG_RANK, 1, (uint32_t)r, (uint32_t)t, mkeys);
+    draw_block(p, TAG_RANK, 2, (uint32_t)r, (uint32_t)t, mkeys + 4);
+    memset(dw, 0, sizeof(*dw));
+    dw->in_dr = in_subset((uint32_t)r, (uint32_t)ps, (uint32_t)m_dr, dr_keys);
+    dw->u_op = oracle_uniform(s0[0]);
+    dw->u_f = oracle_uniform(s0[1]);
+    dw->u_rep = oracle_uniform(s0[2]);
+    /* "+-": one fair sign per protozoan and use */
+    dw->sgn = oracle_uniform(s0[3]) < 0.5 ? 1.0 : -1.0;
+    dw->mask = mask;
+    dw->U = U;
+    const int op = decide_op(p, t, r, dw);
+
+    int m = D;
+    if (op == OR_REPRODUCTION) {
+        double u_mr = oracle_uniform(draw_word(p, TAG_RANK, 3, 0, (uint32_t)r, (uint32_t)t));
+        m = (int)ceil((double)D * u_mr);
+    } else if (op != OR_DORMANCY) {
+        m = (int)ceil((double)D * (double)i / (double)ps);
+    }
+    if (op != OR_DORMANCY)
+        oracle_subset_mask((uint32_t)D, (uint32_t)m, mkeys, mask);
+    if (op == OR_AUTOTROPH) {
+        dw->j = (int)oracle_bounded(draw_word(p, TAG_RANK, 3, 1, (uint32_t)r, (uint32_t)t),
+                                    (uint32_t)ps);
+        for (int k = 1; k <= np; ++k) {
+            uint32_t wm = draw_word(p, TAG_RANK, 3, (uint32_t)(2 * k), (uint32_t)r, (uint32_t)t);
+            uint32_t wp = draw_word(p, TAG_RANK, 3, (uint32_t)(2 * k + 1), (uint32_t)r,
+                                    (uint32_t)t);
+            dw->km[k - 1] = (r == 0) ? r : (int)oracle_bounded(wm, (uint32_t)r);
+            dw->kp[k - 1] = (r == ps - 1) ? r
+                            : r + 1 + (int)oracle_bounded(wp, (uint32_t)(ps - 1 - r));
+        }
+    } else {
+        /* Eqs. (1), (2), (9) read Rand on (a subset of) the coordinates */
+        for (int d = 0; d < D; ++d)
+            U[d] = oracle_uniform(draw_word(p, TAG_ELEM, 0, (uint32_t)d, (uint32_t)r,
+                                            (uint32_t)t));
+    }
+    *m_out = m;
+    return op;
+}
+
+/* ------------------------------------------------------------------ */
+/* One iteration t (1-based) of Algorithm 1, synchronous: every         */
+/* candidate is built from the population as it stood when the          */
+/* iteration began.  script == NULL draws from the Philox stream;       */
+/* otherwise script[r] holds rank r's draws (Dr membership included).   */
+/* ------------------------------------------------------------------ */
+static int step_impl(const oracle_problem *p, int32_t t, double *X, double *F,
+                     const oracle_draws *script, oracle_trace *tr)
+{
+    const int D = p->dim, ps = p->pop, np = p->np, T = p->max_iter;
+    if (t < 1 || t > T || np < 1 || np > OR_MAX_NP)
         return -1;
 
     /* Sort the protozoa by fitness (Algorithm 1).  perm[r] is the id of
@@ -485,146 +667,48 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
 
     /* pf = pf_max * rand (Eq. (11)); Dr = randperm(ps, ceil(ps * pf)). */
     uint32_t w_it[4], dr_keys[8];
-    draw_block(p, TAG_ITER, 0, 0, (uint32_t)t, w_it);
-    draw_block(p, TAG_ITER, 1, 0, (uint32_t)t, dr_keys);
-    draw_block(p, TAG_ITER, 2, 0, (uint32_t)t, dr_keys + 4);
-    double pf = p->pf_max * oracle_uniform(w_it[0]);
-    int m_dr = (int)ceil((double)ps * pf);
+    int m_dr = 0;
+    if (!script) {
+        draw_block(p, TAG_ITER, 0, 0, (uint32_t)t, w_it);
+        draw_block(p, TAG_ITER, 1, 0, (uint32_t)t, dr_keys);
+        draw_block(p, TAG_ITER, 2, 0, (uint32_t)t, dr_keys + 4);
+        double pf = p->pf_max * oracle_uniform(w_it[0]);
+        m_dr = (int)ceil((double)ps * pf);
+    } else {
+        for (int r = 0; r < ps; ++r)
+            m_dr += script[r].in_dr ? 1 : 0;
+    }
     if (tr && tr->dr_count)
         tr->dr_count[0] = m_dr;
 
-    /* Eqs. (4), (9), (12): the iteration-dependent scalars. */
-    double p_ah = 0.5 * (1.0 + cos(((double)t / (double)T) * OR_PI));
-    double f_scale = 1.0 + cos(((double)t / (double)T) * OR_PI);
-    double near_scale = 1.0 - (double)t / (double)T;
-
     double *Y = (double *)malloc(sizeof(double) * (size_t)ps * D);
     double *acc = (double *)malloc(sizeof(double) * (size_t)D);
+    double *U = (double *)malloc(sizeof(double) * (size_t)D);
     uint8_t *mask = (uint8_t *)malloc((size_t)D);
 
     for (int r = 0; r < ps; ++r) {
         const int id = perm[r];
-        const int i = r + 1;                              /* the paper's rank */
-        const double *xi = &X[(size_t)id * D];
-        double *y = &Y[(size_t)id * D];
-
-        uint32_t s0[4], mkeys[8];
-        draw_block(p, TAG_RANK, 0, (uint32_t)r, (uint32_t)t, s0);
-        draw_block(p, TAG_RANK, 1, (uint32_t)r, (uint32_t)t, mkeys);
-        draw_block(p, TAG_RANK, 2, (uint32_t)r, (uint32_t)t, mkeys + 4);
-        const double u_op = oracle_uniform(s0[0]);
-        const double u_f = oracle_uniform(s0[1]);
-        const double u_rep = oracle_uniform(s0[2]);
-        /* "+-": one fair sign per protozoan and use */
-        const double sgn = oracle_uniform(s0[3]) < 0.5 ? 1.0 : -1.0;
-
-        int op, m = D;
         int32_t *nbrow = tr && tr->nb ? &tr->nb[(size_t)id * (1 + 2 * np)] : NULL;
         if (nbrow)
             for (int q = 0; q < 1 + 2 * np; ++q)
                 nbrow[q] = -1;
-
-        if (in_subset((uint32_t)r, (uint32_t)ps, (uint32_t)m_dr, dr_keys)) {
-            /* Eq. (13) */
-            /* Eq. (13) as printed; the variant flips the sign in front of
-             * the cosine (the reading that makes the worst ranks, not the
-             * best, the likeliest to go dormant) */
-            double c_dr = cos((1.0 - (double)i / (double)ps) * OR_PI);
-            double p_dr = p->pdr_plus ? 0.5 * (1.0 + c_dr) : 0.5 * (1.0 - c_dr);
-            if (p_dr > u_op) {
-                /* dormancy, Eq. (1): a fresh protozoan in the bounds */
-                op = OR_DORMANCY;
-                for (int d = 0; d < D; ++d) {
-                    double U = oracle_uniform(draw_word(p, TAG_ELEM, 0, (uint32_t)d,
-                                                       (uint32_t)r, (uint32_t)t));
-                    y[d] = p->lb[d] + U * (p->ub[d] - p->lb[d]);
-                }
-            } else {
-                /* reproduction, Eqs. (2), (3) */
-                op = OR_REPRODUCTION;
-                double u_mr = oracle_uniform(draw_word(p, TAG_RANK, 3, 0, (uint32_t)r,
-                                                       (uint32_t)t));
-                m = (int)ceil((double)D * u_mr);
-                oracle_subset_mask((uint32_t)D, (uint32_t)m, mkeys, mask);
-                for (int d = 0; d < D; ++d) {
-                    if (mask[d]) {
-                        double U = oracle_uniform(draw_word(p, TAG_ELEM, 0, (uint32_t)d,
-                                                           (uint32_t)r, (uint32_t)t));
-                        double R = p->lb[d] + U * (p->ub[d] - p->lb[d]);
-                        y[d] = xi[d] + (sgn * u_rep) * R;
-                    } else {
-                        y[d] = xi[d];
-                    }
-                }
+        oracle_draws own;
+        const oracle_draws *dw;
+        int op, m;
+        if (script) {
+            dw = &script[r];
+            op = decide_op(p, t, r, dw);
+            m = D;
+            if (op != OR_DORMANCY) {
+                m = 0;
+                for (int d = 0; d < D; ++d)
+                    m += dw->mask[d] ? 1 : 0;
             }
         } else {
-            /* foraging: Eq. (4) factor and Eq. (5) mask of ceil(D*i/ps) dims */
-            const double fac = u_f * f_scale;
-            m = (int)ceil((double)D * (double)i / (double)ps);
-            oracle_subset_mask((uint32_t)D, (uint32_t)m, mkeys, mask);
-            for (int d = 0; d < D; ++d)
-                acc[d] = 0.0;
-            if (p_ah > u_op) {
-                /* autotroph, Eqs. (6), (7).  j is any rank; k- a strictly
-                 * better rank (itself for the best); k+ a strictly worse
-                 * rank (itself for the worst). */
-                op = OR_AUTOTROPH;
-                uint32_t wj = draw_word(p, TAG_RANK, 3, 1, (uint32_t)r, (uint32_t)t);
-                int j = (int)oracle_bounded(wj, (uint32_t)ps);
-                if (nbrow)
-                    nbrow[0] = j;
-                for (int k = 1; k <= np; ++k) {
-                    uint32_t wm = draw_word(p, TAG_RANK, 3, (uint32_t)(2 * k),
-                                            (uint32_t)r, (uint32_t)t);
-                    uint32_t wp = draw_word(p, TAG_RANK, 3, (uint32_t)(2 * k + 1),
-                                            (uint32_t)r, (uint32_t)t);
-                    int km = (r == 0) ? r : (int)oracle_bounded(wm, (uint32_t)r);
-                    int kp = (r == ps - 1) ? r
-                             : r + 1 + (int)oracle_bounded(wp, (uint32_t)(ps - 1 - r));
-                    if (nbrow) {
-                        nbrow[2 * k - 1] = km;
-                        nbrow[2 * k] = kp;
-                    }
-                    const int idm = perm[km], idp = perm[kp];
-                    double wa = exp(-fabs(F[idm] / (F[idp] + eps)));
-                    for (int d = 0; d < D; ++d)
-                        acc[d] = acc[d] + wa * (X[(size_t)idm * D + d] - X[(size_t)idp * D + d]);
-                }
-                const double *xj = &X[(size_t)perm[j] * D];
-                for (int d = 0; d < D; ++d) {
-                    if (mask[d])
-                        y[d] = xi[d] + fac * ((xj[d] - xi[d]) + acc[d] / (double)np);
-                    else
-                        y[d] = xi[d];
-                }
-            } else {
-                /* heterotroph, Eqs. (8)-(10); ranks i-k and i+k are held
-                 * inside [1, ps]. */
-                op = OR_HETEROTROPH;
-                for (int k = 1; k <= np; ++k) {
-                    int a = r - k < 0 ? 0 : r - k;
-                    int b = r + k > ps - 1 ? ps - 1 : r + k;
-                    if (nbrow) {
-                        nbrow[2 * k - 1] = a;
-                        nbrow[2 * k] = b;
-                    }
-                    const int ida = perm[a], idb = perm[b];
-                    double wh = exp(-fabs(F[ida] / (F[idb] + eps)));
-                    for (int d = 0; d < D; ++d)
-                        acc[d] = acc[d] + wh * (X[(size_t)ida * D + d] - X[(size_t)idb * D + d]);
-                }
-                for (int d = 0; d < D; ++d) {
-                    if (mask[d]) {
-                        double U = oracle_uniform(draw_word(p, TAG_ELEM, 0, (uint32_t)d,
-                                                           (uint32_t)r, (uint32_t)t));
-                        double xnear = (1.0 + (sgn * U) * near_scale) * xi[d];
-                        y[d] = xi[d] + fac * ((xnear - xi[d]) + acc[d] / (double)np);
-                    } else {
-                        y[d] = xi[d];
-                    }
-                }
-            }
+            op = philox_draws(p, t, r, m_dr, dr_keys, &own, mask, U, &m);
+            dw = &own;
         }
+        candidate(p, t, r, op, perm, X, F, dw, acc, &Y[(size_t)id * D], nbrow);
         if (tr && tr->op)
             tr->op[id] = op;
         if (tr && tr->mcount)
@@ -643,10 +727,28 @@ OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double 
     }
     free(Fy);
     free(acc);
+    free(U);
     free(mask);
     free(Y);
     free(perm);
     return 0;
+}
+
+OR_EXPORT int oracle_step(const oracle_problem *p, int32_t t, double *X, double *F,
+                          oracle_trace *tr)
+{
+    return step_impl(p, t, X, F, NULL, tr);
+}
+
+/* The same iteration with every draw supplied: script[r] (r = 0-based
+ * rank after the sort) gives rank r's Dr membership, rands, sign,
+ * neighbour ranks, mask and Rand vector.  Nothing is drawn. */
+OR_EXPORT int oracle_step_scripted(const oracle_problem *p, int32_t t, double *X, double *F,
+                                   const oracle_draws *script, oracle_trace *tr)
+{
+    if (!script)
+        return -1;
+    return step_impl(p, t, X, F, script, tr);
 }
 
 /* Best protozoan: the minimum in the sort order (lowest id on ties). */
