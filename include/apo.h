@@ -102,8 +102,9 @@ typedef struct {
 } apo_options;
 
 /* Device bytes apo_create needs for these sizes and options (0 if the
- * arguments are invalid).  Nothing is allocated. */
-size_t apo_workspace_bytes(int32_t dim, int32_t pop, int32_t np, const apo_options *opt);
+ * arguments are invalid).  The layout does not depend on np.  Nothing is
+ * allocated. */
+size_t apo_workspace_bytes(int32_t dim, int32_t pop, const apo_options *opt);
 
 /* Create an optimiser (Algorithm 1, input and initialisation).
  *   dim     D >= 1 coordinates per protozoan
@@ -116,9 +117,12 @@ size_t apo_workspace_bytes(int32_t dim, int32_t pop, int32_t np, const apo_optio
  *   out     receives the handle
  * Draws the initial population uniformly in the bounds and evaluates it
  * (ps function evaluations).  Asynchronous on the handle's stream.
- * Errors: APO_E_INVAL (bad argument), APO_E_UNSUPPORTED (sizes beyond
- * dim <= 1024 for elementwise objectives, dim <= 256 (FP64) or 512 (FP32)
- * for rotated ones, pop > 65536), APO_E_NOMEM, APO_E_DEVICE. */
+ * Errors: APO_E_INVAL (bad argument), APO_E_UNSUPPORTED (sizes the kernels
+ * are not built for: pop > 65536; elementwise objectives above dim 1024;
+ * rotated objectives above dim 256 in APO_FP64 and above 1024 in APO_FP32
+ * and APO_BF16 (above 512 the product runs in the GEMM form, separable
+ * objectives only: no Rosenbrock); Kapur / Otsu above 512 thresholds),
+ * APO_E_NOMEM, APO_E_DEVICE. */
 int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int32_t np,
                double pf_max, uint64_t seed, const apo_options *opt, apo_t **out);
 
@@ -131,7 +135,9 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
 int apo_step(apo_t *h);
 
 /* Up to iters more iterations (clipped to max_iter - t), launched as a
- * replayed HIP graph.  Returns the number executed (>= 0) or a status. */
+ * replayed HIP graph.  Returns the number executed (>= 0) or a status.  The
+ * graphs are captured on the first call; apo_run(h, 0) captures them and
+ * executes nothing (so a later timed call does not include the capture). */
 int apo_run(apo_t *h, int32_t iters);
 
 /* The best protozoan (lowest fitness; NaN never wins; lowest id on ties):
@@ -171,10 +177,17 @@ int apo_get_trace(apo_t *h, double *Y, double *Fy, int32_t *op, int32_t *perm);
 int apo_time_kernels(apo_t *h, int32_t n, double *avg_us);
 
 /* 256-bin grey-level histogram of an 8-bit image (the input of the Kapur and
- * Otsu objectives): d_img device [n] bytes, d_hist device [256] uint32
- * counts (overwritten), stream a hipStream_t or NULL (null stream).
- * n < 2^32.  Asynchronous.  APO_E_INVAL for NULL pointers. */
-int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint32_t *d_hist, void *stream);
+ * Otsu objectives; Section 5.2 reduces the image to a threshold criterion):
+ *   d_img      device [n] bytes (any alignment)
+ *   n          pixels, n < 2^32
+ *   host_hist  host [256] uint64 counts (overwritten): count of grey level g
+ *   stream     hipStream_t the kernels run on, or NULL (null stream)
+ * Allocates a device scratch buffer of about 530 KB for the call (partial
+ * counts), runs the histogram kernel and copies the counts to the host;
+ * synchronises the stream before returning.  Counts are exact.  Errors:
+ * APO_E_INVAL (NULL host_hist, NULL d_img with n > 0, n >= 2^32),
+ * APO_E_NOMEM, APO_E_DEVICE. */
+int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint64_t *host_hist, void *stream);
 
 /* Stage times of a handle whose step runs in the GEMM form (rotated
  * objectives above 512 dimensions in binary32, and every APO_BF16 handle):

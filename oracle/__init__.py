@@ -78,6 +78,10 @@ def _configure(L):
     L.oracle_run.restype = C.c_int32
     L.oracle_run.argtypes = [P(_Problem), C.c_int32, C.c_int32, P(C.c_double), P(C.c_double)]
     L.oracle_histogram_u8.argtypes = [P(C.c_uint8), C.c_uint64, P(C.c_uint64)]
+    if hasattr(L, "oracle_set_threads"):
+        L.oracle_set_threads.restype = C.c_int32
+        L.oracle_set_threads.argtypes = [C.c_int32]
+        L.oracle_set_threads(1)
     return L
 
 
@@ -94,6 +98,12 @@ def lib():
             _build.build()
         _lib = _configure(C.CDLL(_build.LIB))
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Spread the oracle's loops over protozoa across n threads (results are
+    bit-identical for every n); returns the count in effect."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def _ptr(a: Optional[np.ndarray], ctype):

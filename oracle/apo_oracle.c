@@ -33,11 +33,21 @@
  *
  * Everything is IEEE binary64, evaluated in the order the formulas are
  * written; the file is compiled with -ffp-contract=off.
+ *
+ * Threads: the protozoa of one iteration are independent given the
+ * population at the start of the iteration (the synchronous reading of
+ * Algorithm 1's parallel loop), so the per-rank candidates and the
+ * evaluations may be spread over OpenMP threads (oracle_set_threads); every
+ * value is computed by the same code in the same order whatever the thread
+ * count, so results are bit-identical.  The default is one thread.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_EXPORT __attribute__((visibility("default")))
 
@@ -428,6 +438,7 @@ OR_EXPORT void oracle_rank_order(int32_t pop, const double *F, int32_t *perm)
 OR_EXPORT void oracle_init(const oracle_problem *p, double *X, double *F)
 {
     int D = p->dim;
+#pragma omp parallel for schedule(static)
     for (int id = 0; id < p->pop; ++id) {
         for (int d = 0; d < D; ++d) {
             uint32_t w = draw_word(p, TAG_INIT, 0, (uint32_t)d, (uint32_t)id, 0);
@@ -447,6 +458,7 @@ OR_EXPORT void oracle_finish(const oracle_problem *p, double *X, double *F, doub
                              double *Fy, uint8_t *accepted)
 {
     int D = p->dim;
+#pragma omp parallel for schedule(static)
     for (int id = 0; id < p->pop; ++id) {
         double *y = &Y[(size_t)id * D];
         for (int d = 0; d < D; ++d)        /* saturate: 13.53 -> 10 in the example */
@@ -682,37 +694,45 @@ static int step_impl(const oracle_problem *p, int32_t t, double *X, double *F,
         tr->dr_count[0] = m_dr;
 
     double *Y = (double *)malloc(sizeof(double) * (size_t)ps * D);
-    double *acc = (double *)malloc(sizeof(double) * (size_t)D);
-    double *U = (double *)malloc(sizeof(double) * (size_t)D);
-    uint8_t *mask = (uint8_t *)malloc((size_t)D);
 
-    for (int r = 0; r < ps; ++r) {
-        const int id = perm[r];
-        int32_t *nbrow = tr && tr->nb ? &tr->nb[(size_t)id * (1 + 2 * np)] : NULL;
-        if (nbrow)
-            for (int q = 0; q < 1 + 2 * np; ++q)
-                nbrow[q] = -1;
-        oracle_draws own;
-        const oracle_draws *dw;
-        int op, m;
-        if (script) {
-            dw = &script[r];
-            op = decide_op(p, t, r, dw);
-            m = D;
-            if (op != OR_DORMANCY) {
-                m = 0;
-                for (int d = 0; d < D; ++d)
-                    m += dw->mask[d] ? 1 : 0;
+#pragma omp parallel
+    {
+        /* per-thread scratch: the pair sum, Rand and the mask of one rank */
+        double *acc = (double *)malloc(sizeof(double) * (size_t)D);
+        double *U = (double *)malloc(sizeof(double) * (size_t)D);
+        uint8_t *mask = (uint8_t *)malloc((size_t)D);
+#pragma omp for schedule(static)
+        for (int r = 0; r < ps; ++r) {
+            const int id = perm[r];
+            int32_t *nbrow = tr && tr->nb ? &tr->nb[(size_t)id * (1 + 2 * np)] : NULL;
+            if (nbrow)
+                for (int q = 0; q < 1 + 2 * np; ++q)
+                    nbrow[q] = -1;
+            oracle_draws own;
+            const oracle_draws *dw;
+            int op, m;
+            if (script) {
+                dw = &script[r];
+                op = decide_op(p, t, r, dw);
+                m = D;
+                if (op != OR_DORMANCY) {
+                    m = 0;
+                    for (int d = 0; d < D; ++d)
+                        m += dw->mask[d] ? 1 : 0;
+                }
+            } else {
+                op = philox_draws(p, t, r, m_dr, dr_keys, &own, mask, U, &m);
+                dw = &own;
             }
-        } else {
-            op = philox_draws(p, t, r, m_dr, dr_keys, &own, mask, U, &m);
-            dw = &own;
+            candidate(p, t, r, op, perm, X, F, dw, acc, &Y[(size_t)id * D], nbrow);
+            if (tr && tr->op)
+                tr->op[id] = op;
+            if (tr && tr->mcount)
+                tr->mcount[id] = m;
         }
-        candidate(p, t, r, op, perm, X, F, dw, acc, &Y[(size_t)id * D], nbrow);
-        if (tr && tr->op)
-            tr->op[id] = op;
-        if (tr && tr->mcount)
-            tr->mcount[id] = m;
+        free(acc);
+        free(U);
+        free(mask);
     }
 
     double *Fy = (double *)malloc(sizeof(double) * (size_t)ps);
@@ -726,9 +746,6 @@ static int step_impl(const oracle_problem *p, int32_t t, double *X, double *F,
             memcpy(tr->perm, perm, sizeof(int32_t) * (size_t)ps);
     }
     free(Fy);
-    free(acc);
-    free(U);
-    free(mask);
     free(Y);
     free(perm);
     return 0;
@@ -749,6 +766,20 @@ OR_EXPORT int oracle_step_scripted(const oracle_problem *p, int32_t t, double *X
     if (!script)
         return -1;
     return step_impl(p, t, X, F, script, tr);
+}
+
+/* Threads the oracle's loops over protozoa use (n > 0 sets the count);
+ * returns the count in effect (1 in a build without OpenMP). */
+OR_EXPORT int32_t oracle_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* Best protozoan: the minimum in the sort order (lowest id on ties). */

@@ -54,7 +54,7 @@ def workspace_bytes(dim, pop, np_pairs=1, max_iter=1, precision="fp64", kind="sp
     rot = np.eye(dim) if rotated else None
     hist = np.ones(256, np.uint64) if kind in ("kapur", "otsu") else None
     o = _options(max_iter, precision, kind, None, rot, hist, 0, APO_FLAG_TRACE if trace else 0)
-    return int(lib().apo_workspace_bytes(int(dim), int(pop), int(np_pairs), C.byref(o)))
+    return int(lib().apo_workspace_bytes(int(dim), int(pop), C.byref(o)))
 
 
 class APO:
@@ -82,7 +82,7 @@ class APO:
         flags = (APO_FLAG_TRACE if trace else 0) | (APO_FLAG_PDR_PLUS if pdr_plus else 0)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         o = _options(max_iter, precision, kind, shift, rot, hist, run_id, flags)
-        nbytes = int(lib().apo_workspace_bytes(self.dim, self.pop, int(np_pairs), C.byref(o)))
+        nbytes = int(lib().apo_workspace_bytes(self.dim, self.pop, C.byref(o)))
         if nbytes == 0:
             raise APOError(-1, "apo_workspace_bytes")
         self._ws = torch.empty(nbytes, dtype=torch.uint8, device=torch.cuda.current_device())
@@ -135,6 +135,8 @@ class APO:
         return True
 
     def run(self, iters: Optional[int] = None) -> int:
+        """Up to ``iters`` iterations (default: the rest of the budget) as
+        replayed graphs; ``run(0)`` only captures the graphs."""
         n = self.max_iter if iters is None else int(iters)
         return _check(lib().apo_run(self._h, n), "apo_run")
 
@@ -287,16 +289,16 @@ class Batch:
         self.close()
 
 
-def histogram_u8(img, stream=None):
-    """256-bin histogram (uint32 counts, device tensor) of a uint8 device
-    tensor, computed by the library's histogram kernel."""
+def histogram_u8(img, stream=None) -> np.ndarray:
+    """256-bin histogram (numpy uint64 counts) of a uint8 device tensor,
+    computed by the library's histogram kernel (``apo_histogram_u8``)."""
     torch = _torch()
     if img.dtype != torch.uint8 or not img.is_cuda:
         raise ValueError("histogram_u8 needs a uint8 device tensor")
     img = img.contiguous()
-    out = torch.empty(256, dtype=torch.int32, device=img.device)
+    out = np.zeros(256, dtype=np.uint64)
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().apo_histogram_u8(C.c_void_p(img.data_ptr()), img.numel(),
-                                  C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)),
-           "apo_histogram_u8")
+                                  out.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                  C.c_void_p(s.cuda_stream)), "apo_histogram_u8")
     return out

@@ -71,7 +71,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     P, d, i32, u64, vp = C.POINTER, C.c_double, C.c_int32, C.c_uint64, C.c_void_p
     L.apo_workspace_bytes.restype = C.c_size_t
-    L.apo_workspace_bytes.argtypes = [i32, i32, i32, P(Options)]
+    L.apo_workspace_bytes.argtypes = [i32, i32, P(Options)]
     L.apo_create.restype = C.c_int
     L.apo_create.argtypes = [i32, P(d), P(d), i32, i32, d, u64, P(Options), P(vp)]
     for name in ("apo_step", "apo_destroy"):

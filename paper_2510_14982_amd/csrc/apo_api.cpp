@@ -45,11 +45,9 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     Layout L;
     std::memset(&L, 0, sizeof(L));
     const size_t es = o.precision == APO_FP64 ? 8 : 4;
-    L.Dp = (int)align_up((size_t)dim, 64 / es);
-    L.Nt = (dim + 15) / 16;
-    // k-steps of 4, padded with zeros to a multiple of 8 so the matrix-core
-    // loop runs unguarded in blocks of 8
-    L.Ks = ((dim + 3) / 4 + 7) / 8 * 8;
+    L.Dp = apok::row_stride(dim, (int)es);
+    L.Nt = apok::col_tiles(dim);
+    L.Ks = apok::k_steps(dim);   // zero-padded so the matrix-core loop runs unguarded
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -103,6 +101,13 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     return L;
 }
 
+// Rows per workgroup of a single handle's tiled step: wide tiles only when
+// the run alone still gives every CU a workgroup.
+int single_tile_rows(int dim, int pop) {
+    const int wide = apok::tile_rows_wide(apok::lanes_for_dim(dim));
+    return (wide > 16 && pop >= 256 * wide) ? wide : 16;
+}
+
 int check_args(int32_t dim, const double *lb, const double *ub, int32_t pop, int32_t np,
                double pf_max, const apo_options *opt) {
     if (!opt || !lb || !ub) return APO_E_INVAL;
@@ -140,10 +145,34 @@ int check_args(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     } else if (tile) {
         const int lim = is_threshold(kind) ? 512 : (opt->precision == APO_FP64 ? 256 : 512);
         if (dim > lim) return APO_E_UNSUPPORTED;
-    } else if (apok::chunks_for_dim(dim) < 0) {
+        const int G = apok::lanes_for_dim(dim);
+        if (!apok::tile_shape_ok(dim, G, apok::chunks_for(dim, G), single_tile_rows(dim, pop),
+                                 opt->precision == APO_FP64 ? 8 : 4))
+            return APO_E_UNSUPPORTED;
+    } else if (!apok::elem_shape_built(apok::lanes_for_dim(dim), apok::chunks_for_dim(dim))) {
         return APO_E_UNSUPPORTED;
     }
     return APO_OK;
+}
+
+// The tiled-step shape of a batch member: its batch lane count (or the
+// dimension's), one row per lane group, the chunks that cover D.  APO_OK if
+// the library has that kernel and its LDS fits, else APO_E_UNSUPPORTED.
+struct MemberShape {
+    int lanes;   // 0: the dimension's own count
+    int G, NCH, rows;
+};
+
+int batch_member_shape(const apo_run_desc &d, MemberShape &m) {
+    const bool rotated = d.opt.objective.rot != nullptr;
+    const int es = d.opt.precision == APO_FP64 ? 8 : 4;
+    m.lanes = apok::batch_lanes(d.dim, rotated, d.opt.objective.kind == APO_ROSENBROCK, es);
+    m.G = m.lanes ? m.lanes : apok::lanes_for_dim(d.dim);
+    m.NCH = apok::chunks_for(d.dim, m.G);
+    m.rows = apok::tile_rows_wide(m.G);
+    const bool tiled = rotated || is_threshold(d.opt.objective.kind);
+    if (!tiled) return APO_OK;   // the elementwise step (shape checked by check_args)
+    return apok::tile_shape_ok(d.dim, m.G, m.NCH, m.rows, es) ? APO_OK : APO_E_UNSUPPORTED;
 }
 
 template <typename T>
@@ -269,6 +298,9 @@ int batch_layout(int32_t n, const apo_run_desc *runs, BatchLayout &B) {
         const int chk = check_args(d.dim, d.lb, d.ub, d.pop, d.np, d.pf_max, &d.opt);
         if (chk != APO_OK) return chk;
         if (gemm_form(d.dim, d.opt)) return APO_E_UNSUPPORTED;   // not in batches
+        MemberShape ms;
+        const int shp = batch_member_shape(d, ms);
+        if (shp != APO_OK) return shp;
         const Layout L = make_layout(d.dim, d.pop, d.opt);
         B.run_off[i] = off;
         B.run_bytes[i] = L.total;
@@ -384,11 +416,20 @@ hipError_t batch_enqueue(apo_batch *b, int32_t iters) {
                 if (e != hipSuccess) return e;
             }
             e = hipStreamWaitEvent(b->side[k], b->fork_ev, 0);
-            if (e == hipSuccess)
-                e = apok::launch_step_batch(b->runs[r.proto]->p, r.fp64, bl, b->side[k]);
-            if (e == hipSuccess) e = hipEventRecord(b->join_ev[k], b->side[k]);
-            if (e != hipSuccess) return e;
-            ++k;
+            if (e == hipSuccess) {
+                ++k;   // side stream k has joined the fork: it must be joined back
+                e = apok::launch_step_batch(b->runs[r.proto]->p, r.fp64, bl, b->side[k - 1]);
+            }
+            if (e == hipSuccess) e = hipEventRecord(b->join_ev[k - 1], b->side[k - 1]);
+            if (e != hipSuccess) {
+                // join every forked branch back (a capture must not end with
+                // unjoined work) and report the first error
+                for (size_t j = 0; j < k; ++j) {
+                    (void)hipEventRecord(b->join_ev[j], b->side[j]);
+                    (void)hipStreamWaitEvent(b->stream, b->join_ev[j], 0);
+                }
+                return e;
+            }
         }
         for (size_t j = 0; j < k; ++j) {
             const hipError_t e = hipStreamWaitEvent(b->stream, b->join_ev[j], 0);
@@ -450,8 +491,8 @@ int batch_destroy_impl(apo_batch *b) {
 
 extern "C" {
 
-size_t apo_workspace_bytes(int32_t dim, int32_t pop, int32_t np, const apo_options *opt) {
-    if (!opt || dim < 1 || pop < 2 || np < 1 || opt->max_iter < 1) return 0;
+size_t apo_workspace_bytes(int32_t dim, int32_t pop, const apo_options *opt) {
+    if (!opt || dim < 1 || pop < 2 || opt->max_iter < 1) return 0;
     return make_layout(dim, pop, *opt).total;
 }
 
@@ -539,11 +580,7 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     p.rotated = opt->objective.rot != nullptr;
     p.Nt = L.Nt;
     p.Ks = L.Ks;
-    {
-        // wide tiles only when the run alone still gives every CU a workgroup
-        const int wide = apok::tile_rows_wide(apok::lanes_for_dim(dim));
-        p.rows = (wide > 16 && pop >= 256 * wide) ? wide : 16;
-    }
+    p.rows = single_tile_rows(dim, pop);
     p.rank_lds = pop <= 256 ? 1 : 0;   // one workgroup ranks the whole run
     p.gemm = gf ? 1 : 0;
     p.trace = (opt->flags & APO_FLAG_TRACE) ? 1 : 0;
@@ -769,13 +806,13 @@ int apo_run(apo_t *h, int32_t iters) {
     if (h->poisoned) return APO_E_DEVICE;
     int32_t n = h->T - h->t;
     if (iters < n) n = iters;
-    if (n <= 0) return 0;
-    if (!h->graph_tried) {
+    if (!h->graph_tried) {   // apo_run(h, 0) only does this
         h->graph_tried = true;
         capture_iterations(h, 1, &h->graph[0], &h->graph_exec[0]);
         if (h->graph_exec[0] && h->T >= kGraphBlock)
             capture_iterations(h, kGraphBlock, &h->graph[1], &h->graph_exec[1]);
     }
+    if (n <= 0) return 0;
     int32_t done = 0;
     while (done < n) {
         if (h->graph_exec[1] && n - done >= kGraphBlock) {
@@ -988,13 +1025,19 @@ int apo_get_trace(apo_t *h, double *Y, double *Fy, int32_t *op, int32_t *perm) {
     return APO_OK;
 }
 
-int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint32_t *d_hist, void *stream) {
-    if (!d_hist || (!d_img && n > 0) || n >= (1ull << 32)) return APO_E_INVAL;
-    if (apok::launch_histogram(d_img, n, d_hist, (hipStream_t)stream) != hipSuccess)
-        return APO_E_DEVICE;
-    return APO_OK;
+int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint64_t *host_hist, void *stream) {
+    if (!host_hist || (!d_img && n > 0) || n >= (1ull << 32)) return APO_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *scratch = nullptr;
+    if (hipMalloc((void **)&scratch, apok::histogram_scratch_bytes()) != hipSuccess)
+        return APO_E_NOMEM;
+    bool ok = apok::launch_histogram(d_img, n, scratch, s) == hipSuccess &&
+              hipMemcpyAsync(host_hist, scratch + apok::histogram_out_offset(), 256 * 8,
+                             hipMemcpyDeviceToHost, s) == hipSuccess &&
+              hipStreamSynchronize(s) == hipSuccess;
+    ok = hipFree(scratch) == hipSuccess && ok;
+    return ok ? APO_OK : APO_E_DEVICE;
 }
-
 
 size_t apo_batch_workspace_bytes(int32_t n, const apo_run_desc *runs) {
     BatchLayout B;
@@ -1048,17 +1091,13 @@ int apo_batch_create(int32_t n, const apo_run_desc *runs, const apo_batch_option
         }
         h->batch_view = true;
         // a batch fills the GPU with runs: fewer, fuller workgroups per run
-        // (rotated separable objectives: the tiled step takes 4 lanes per
-        // protozoan up to 64 dimensions and 8 up to 128, with up to four
-        // chunks each, 128 or 64 rows a workgroup -- their results do not
-        // depend on the lane count, since candidates are elementwise, masks
-        // are sets and the objective is summed from the matrix-core tiles
-        // in a fixed order; Rosenbrock's lane sums would change)
-        if (h->p.rotated && h->p.kind != apok::K_ROSENBROCK) {
-            if (h->dim > 16 && h->dim <= 64) h->p.lanes = 4;
-            else if (h->dim > 64 && h->dim <= 128) h->p.lanes = 8;
-        }
-        h->p.rows = apok::tile_rows_wide(h->p.lanes ? h->p.lanes : apok::lanes_for_dim(h->dim));
+        // (batch_lanes: fewer lanes per protozoan for rotated separable
+        // objectives, one row per lane group; the shape was checked by
+        // batch_layout)
+        MemberShape ms;
+        (void)batch_member_shape(runs[i], ms);
+        h->p.lanes = ms.lanes;
+        h->p.rows = ms.rows;
         h->p.rank_lds = h->pop <= apok::kRankLdsMax ? 1 : 0;
         b->runs.push_back(h);
     }

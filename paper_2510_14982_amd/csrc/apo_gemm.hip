@@ -647,8 +647,7 @@ static hipError_t launch_cand(const Params &p, const GemmBufs &w, int init, hipS
             launch_k(p, gemm_cand<GG, CC, kMaxNp, BF16>, grid, block, 0, s, p, w, init);     \
         return hipGetLastError();                                                            \
     }
-    APO_CAND(4, 1) APO_CAND(8, 1) APO_CAND(16, 1) APO_CAND(32, 1) APO_CAND(64, 1)
-    APO_CAND(64, 2) APO_CAND(64, 4)
+    APO_ELEM_SHAPES(APO_CAND)
 #undef APO_CAND
     return hipErrorInvalidValue;
 }

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "apo_shape.hpp"
+
 namespace apok {
 
 enum : int32_t { OP_DORMANCY = 0, OP_REPRODUCTION = 1, OP_AUTOTROPH = 2, OP_HETEROTROPH = 3 };
@@ -114,7 +116,14 @@ hipError_t launch_rank(const Params &p, bool fp64, hipStream_t s);
 hipError_t launch_step(const Params &p, bool fp64, hipStream_t s);
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s);
 hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream_t s);
-hipError_t launch_histogram(const uint8_t *img, uint64_t n, uint32_t *hist, hipStream_t s);
+// 256-bin histogram of n bytes into scratch (histogram_scratch_bytes():
+// per-workgroup partial rows, group rows, tickets, then the 256 uint64
+// counts at byte offset histogram_out_offset()).  Stream-ordered, no
+// allocation.
+constexpr int kHistBlocks = 512;   // workgroups of the image pass at most
+constexpr size_t histogram_out_offset() { return ((size_t)(kHistBlocks + 16) * 256 + 64) * 4; }
+size_t histogram_scratch_bytes();
+hipError_t launch_histogram(const uint8_t *img, uint64_t n, void *scratch, hipStream_t s);
 
 // The GEMM form of one step (or of the initial evaluation), and the binary64
 // re-score of one row x (device, binary64) into out[0].
@@ -135,17 +144,12 @@ int step_blocks(const Params &p);              // workgroups of a run's step
 size_t step_lds_bytes(const Params &p, bool fp64);
 int step_shape(const Params &p, bool fp64);    // equal iff one kernel serves both runs
 
-// Lanes per protozoan and 4-element chunks per lane used for a dimension.
-int lanes_for_dim(int dim);
 // The tiled step's lanes per protozoan and chunks per lane for a run (its
 // own lane count when set, else the dimension's); -1 chunks if none fits.
 int tile_lanes(const Params &p);
 int tile_chunks(const Params &p);
 // Largest population the LDS form of the sort takes.
 constexpr int kRankLdsMax = 1024;
-// Rows per workgroup of the wide tiled step for G lanes per protozoan.
-constexpr int tile_rows_wide(int G) { return 512 / G > 16 ? 512 / G : 16; }
-int chunks_for_dim(int dim);
 
 
 }  // namespace apok

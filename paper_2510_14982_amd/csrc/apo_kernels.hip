@@ -305,70 +305,114 @@ __global__ void zero_u32_kernel(uint32_t *a, int n) {
     if (i < n) a[i] = 0u;
 }
 
-// 8-bit histogram.  Sixteen LDS copies per workgroup, chosen by lane % 16,
-// so lanes that meet the same grey level (frequent in images made of
-// uniform regions) mostly hit different copies; copies are 257 words apart
-// so equal levels of different copies sit in different banks.  Each
-// workgroup adds its copies into the output once.  Bytes before the first
-// and after the last 16-byte boundary are counted one by one; the rest is
-// read as 16-byte vectors.
+// 8-bit histogram.  Each workgroup of 512 threads counts its share of the
+// image into LDS: sixteen copies chosen by lane % 16, so lanes that meet the
+// same grey level (frequent in images made of uniform regions) mostly hit
+// different copies; copies are 257 words apart so equal levels of different
+// copies sit in different banks.  Bytes before the first and after the last
+// 16-byte boundary are counted one by one; the rest is read as 16-byte
+// vectors, four per thread in flight.  The 256 counts go to the
+// workgroup's row of the partial table (no global atomics on the bins),
+// which is summed by a two-level ticket tree: the last workgroup of each of
+// up to 16 groups (a device-scope ticket per group) sums the group's rows
+// into a group row, and the last group to finish sums the group rows into
+// the 64-bit output.  Every sum runs in a fixed order.
 constexpr int kHistCopies = 16;
 constexpr int kHistStride = 257;
+constexpr int kHistThreads = 512;
+constexpr int kHistGroups = 16;
+constexpr int kHistUnroll = 4;
 
-__global__ __launch_bounds__(256) void hist_kernel(const uint8_t *img, uint64_t n, uint32_t *hist) {
+struct HistScratch {
+    uint32_t *rows;                // [kHistBlocks][256]
+    uint32_t *group_rows;          // [kHistGroups][256]
+    uint32_t *tickets;             // [kHistGroups + 1]
+    unsigned long long *out;       // [256]
+};
+
+__device__ __forceinline__ void hist_add16(uint32_t *mine, const uint4 &q) {
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) atomicAdd(&mine[(w[j] >> (8 * b)) & 0xFFu], 1u);
+    }
+}
+
+__global__ __launch_bounds__(kHistThreads) void hist_kernel(const uint8_t *img, uint64_t n,
+                                                            HistScratch sc) {
     __shared__ uint32_t h[kHistCopies * kHistStride];
+    __shared__ bool last;
     uint32_t *mine = h + (threadIdx.x & (kHistCopies - 1)) * kHistStride;
-    for (int b = threadIdx.x; b < kHistCopies * kHistStride; b += 256) h[b] = 0u;
+    for (int b = threadIdx.x; b < kHistCopies * kHistStride; b += kHistThreads) h[b] = 0u;
     __syncthreads();
     uint64_t head = (16u - ((uintptr_t)img & 15u)) & 15u;
     if (head > n) head = n;
     const uint64_t nvec = (n - head) / 16;
-    const uint64_t tid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const uint64_t tid = (uint64_t)blockIdx.x * kHistThreads + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * kHistThreads;
     if (tid < head) atomicAdd(&mine[img[tid]], 1u);
     const uint4 *v = (const uint4 *)(img + head);
-    for (uint64_t i = tid; i < nvec; i += stride) {
-        const uint4 q = v[i];
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    for (uint64_t i0 = tid; i0 < nvec; i0 += kHistUnroll * stride) {
+        uint4 q[kHistUnroll];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&mine[(w[j] >> (8 * b)) & 0xFFu], 1u);
+        for (int u = 0; u < kHistUnroll; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * stride;
+            q[u] = i < nvec ? v[i] : make_uint4(0u, 0u, 0u, 0u);
         }
+#pragma unroll
+        for (int u = 0; u < kHistUnroll; ++u)
+            if (i0 + (uint64_t)u * stride < nvec) hist_add16(mine, q[u]);
     }
     for (uint64_t i = head + nvec * 16 + tid; i < n; i += stride) atomicAdd(&mine[img[i]], 1u);
     __syncthreads();
-    for (int b = threadIdx.x; b < 256; b += 256) {
+    const int b = threadIdx.x;   // bins: the first 256 threads
+    if (b < 256) {
         uint32_t s = 0;
 #pragma unroll
         for (int c = 0; c < kHistCopies; ++c) s += h[c * kHistStride + b];
-        if (s) atomicAdd(&hist[b], s);
+        sc.rows[(size_t)blockIdx.x * 256 + b] = s;
+    }
+    // level 1: the last workgroup of this group sums the group's rows
+    const unsigned nb = gridDim.x;
+    const unsigned per = (nb + kHistGroups - 1) / kHistGroups;
+    const unsigned ngroups = (nb + per - 1) / per;
+    const unsigned g = blockIdx.x / per, r0 = g * per, r1 = r0 + per < nb ? r0 + per : nb;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&sc.tickets[g], 1u) == r1 - r0 - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (b < 256) {
+        uint32_t s = 0;
+        for (unsigned r = r0; r < r1; ++r)
+            s += __hip_atomic_load(&sc.rows[(size_t)r * 256 + b], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        sc.group_rows[(size_t)g * 256 + b] = s;
+    }
+    // level 2: the last group sums the group rows
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&sc.tickets[kHistGroups], 1u) == ngroups - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (b < 256) {
+        unsigned long long s = 0;
+        for (unsigned q = 0; q < ngroups; ++q)
+            s += __hip_atomic_load(&sc.group_rows[(size_t)q * 256 + b], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        sc.out[b] = s;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launch selection.
 // ---------------------------------------------------------------------------
-int lanes_for_dim(int dim) {
-    const int need = (dim + 3) / 4;
-    int g = 4;
-    while (g < need && g < 64) g <<= 1;
-    return g;
-}
-
 int tile_lanes(const Params &p) { return p.lanes > 0 ? p.lanes : lanes_for_dim(p.dim); }
 
-int tile_chunks(const Params &p) {
-    if (p.lanes <= 0) return chunks_for_dim(p.dim);
-    const int c = (p.dim + 4 * p.lanes - 1) / (4 * p.lanes);
-    return c <= 1 ? 1 : c <= 2 ? 2 : c <= 4 ? 4 : -1;
-}
-
-int chunks_for_dim(int dim) {
-    const int g = lanes_for_dim(dim);
-    const int c = (dim + 4 * g - 1) / (4 * g);
-    return c <= 1 ? 1 : c <= 2 ? 2 : c <= 4 ? 4 : -1;
-}
+int tile_chunks(const Params &p) { return chunks_for(p.dim, tile_lanes(p)); }
 
 hipError_t launch_elem_f32(const Params &p, int init, hipStream_t s);
 hipError_t launch_elem_f64(const Params &p, int init, hipStream_t s);
@@ -435,12 +479,11 @@ size_t step_lds_bytes(const Params &p, bool fp64) {
     return tile_form(p) ? tile_lds_bytes(p, fp64) : 0;
 }
 
-// Instantiation key: precision, form, lanes, chunks and whether np > 1.
+// Instantiation key: precision, form, lanes, chunks, rows and whether np > 1.
 int step_shape(const Params &p, bool fp64) {
     const bool tf = tile_form(p);
-    return (fp64 ? 1 : 0) | (tf ? 2 : 0) | (p.np > 1 ? 4 : 0) |
-           ((tf ? tile_lanes(p) : lanes_for_dim(p.dim)) << 3) |
-           ((tf ? tile_chunks(p) : chunks_for_dim(p.dim)) << 12) | ((tf ? tile_rows(p) : 0) << 16);
+    return tf ? pack_shape(fp64, true, p.np > 1, tile_lanes(p), tile_chunks(p), tile_rows(p))
+              : pack_shape(fp64, false, p.np > 1, lanes_for_dim(p.dim), chunks_for_dim(p.dim), 0);
 }
 
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s) {
@@ -456,14 +499,35 @@ hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_histogram(const uint8_t *img, uint64_t n, uint32_t *hist, hipStream_t s) {
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(256), 0, s, hist, 256);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n == 0) return e;
-    uint64_t blocks = (n / 16 + 256 * 4 - 1) / (256 * 4);
+// Scratch layout: partial rows, group rows, tickets (padded to 64 words),
+// then the 256 uint64 counts.
+static HistScratch hist_scratch(void *scratch) {
+    HistScratch sc;
+    sc.rows = (uint32_t *)scratch;
+    sc.group_rows = sc.rows + (size_t)kHistBlocks * 256;
+    sc.tickets = sc.group_rows + (size_t)kHistGroups * 256;
+    sc.out = (unsigned long long *)(sc.tickets + 64);
+    return sc;
+}
+
+size_t histogram_scratch_bytes() { return histogram_out_offset() + 256 * 8; }
+
+static int histogram_blocks(uint64_t n) {
+    const uint64_t per = (uint64_t)kHistThreads * kHistUnroll * 16;   // bytes per workgroup pass
+    uint64_t blocks = (n + per - 1) / per;
     if (blocks < 1) blocks = 1;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)blocks), dim3(256), 0, s, img, n, hist);
+    if (blocks > (uint64_t)kHistBlocks) blocks = kHistBlocks;
+    return (int)blocks;
+}
+
+hipError_t launch_histogram(const uint8_t *img, uint64_t n, void *scratch, hipStream_t s) {
+    const HistScratch sc = hist_scratch(scratch);
+    // the tickets start at zero (a fill kernel, not a memset node)
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, sc.tickets, kHistGroups + 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)histogram_blocks(n)), dim3(kHistThreads), 0,
+                       s, img, n, sc);
     return hipGetLastError();
 }
 

@@ -608,16 +608,10 @@ __device__ __forceinline__ double threshold_objective_team(const Params &p, cons
     return -group_sum<32>(part);
 }
 
-// LDS row stride (elements) of the tile's row buffers.  The matrix-core A
-// operand is read as 16-byte vectors by 16 lanes of 16 different rows at a
-// time; a stride of an odd number of 16-byte units puts those rows in 16
-// distinct groups of four banks.  Rows are also written as 16-byte vectors.
+// LDS row stride (elements) of the tile's row buffers (tile_row_stride of
+// apo_shape.hpp on the run's padded sizes).
 __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
-    const int w = p.Dp > 4 * p.Ks ? p.Dp : 4 * p.Ks;
-    const int per = 16 / es;                      // elements per 16 bytes
-    int q = (w + per - 1) / per;
-    if ((q & 1) == 0) ++q;
-    return q * per;
+    return tile_row_stride(p.Dp, p.Ks, es);
 }
 
 // Rows (consecutive ranks) per workgroup of the tiled step: one MFMA row
@@ -909,10 +903,7 @@ inline bool use_tile(const Params &p) {
 }
 
 inline size_t tile_lds_bytes(const Params &p, bool fp64) {
-    const size_t es = fp64 ? 8 : 4, TM = (size_t)tile_rows(p);
-    const size_t LS = (size_t)tile_row_stride(p, (int)es), LZ = (size_t)p.Nt * 16 + 1;
-    const size_t zwords = TM * LZ > TM * ((size_t)p.dim + 1) ? TM * LZ : TM * ((size_t)p.dim + 1);
-    return (3 * TM * LS + zwords + 2 * TM * (size_t)p.Nt) * es;
+    return tile_dynamic_lds(p.dim, tile_rows(p), fp64 ? 8 : 4);
 }
 
 // A launch of one handle (b == nullptr: grid of the run's own blocks, lds
@@ -943,10 +934,7 @@ hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLa
             launch_k(p, step_tile<T, GG, CC, NPMAX, TMM>, grid, block, lds, s, p, init);     \
         return hipGetLastError();                                                            \
     }
-        APO_TILE(4, 1, 16) APO_TILE(8, 1, 16) APO_TILE(16, 1, 16) APO_TILE(32, 1, 16)
-        APO_TILE(64, 1, 16) APO_TILE(64, 2, 16)
-        APO_TILE(4, 1, 128) APO_TILE(8, 1, 64) APO_TILE(16, 1, 32) APO_TILE(4, 2, 128)
-        APO_TILE(4, 4, 128) APO_TILE(8, 4, 64)
+        APO_TILE_SHAPES(APO_TILE)
 #undef APO_TILE
         return hipErrorInvalidValue;
     }
@@ -967,8 +955,7 @@ hipError_t launch_elem_t(const Params &p, int init, hipStream_t s, const BatchLa
             launch_k(p, step_elem<T, GG, CC, NPMAX>, grid, block, 0, s, p, init);            \
         return hipGetLastError();                                                            \
     }
-    APO_ELEM(4, 1) APO_ELEM(8, 1) APO_ELEM(16, 1) APO_ELEM(32, 1) APO_ELEM(64, 1)
-    APO_ELEM(64, 2) APO_ELEM(64, 4)
+    APO_ELEM_SHAPES(APO_ELEM)
 #undef APO_ELEM
     return hipErrorInvalidValue;
 }

@@ -46,12 +46,12 @@ def test_strerror_and_workspace_sizes(L):
     o = _lib.Options()
     o.max_iter = 10
     o.precision = _lib.APO_FP32
-    n1 = L.apo_workspace_bytes(100, 4096, 1, C.byref(o))
+    n1 = L.apo_workspace_bytes(100, 4096, C.byref(o))
     assert n1 >= 2 * 4096 * 112 * 4
     o.flags = _lib.APO_FLAG_TRACE
-    assert L.apo_workspace_bytes(100, 4096, 1, C.byref(o)) > n1
-    assert L.apo_workspace_bytes(0, 4096, 1, C.byref(o)) == 0
-    assert L.apo_workspace_bytes(10, 1, 1, C.byref(o)) == 0
+    assert L.apo_workspace_bytes(100, 4096, C.byref(o)) > n1
+    assert L.apo_workspace_bytes(0, 4096, C.byref(o)) == 0
+    assert L.apo_workspace_bytes(10, 1, C.byref(o)) == 0
 
 
 def _create(L, dim=3, lb=None, ub=None, pop=8, np_pairs=1, pf_max=0.1, max_iter=10,
@@ -112,6 +112,9 @@ def test_null_handles_and_histogram_arguments(L):
     assert L.apo_run(None, 3) == -1
     assert L.apo_destroy(None) == 0
     assert L.apo_histogram_u8(None, 10, None, None) == -1
+    h = np.zeros(256, np.uint64)
+    assert L.apo_histogram_u8(None, 10, h.ctypes.data, None) == -1      # no image
+    assert L.apo_histogram_u8(None, 1 << 32, h.ctypes.data, None) == -1  # n too large
 
 
 def _desc(**kw):

@@ -4,6 +4,9 @@ are parity-unpinned value by value (a near-tie selection flip makes them
 diverge), so they are compared as distributions: two-sided Mann-Whitney U
 with p > 0.01 and medians within 10 %.  The binary64 small run is expected
 to reproduce the oracle seed by seed."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 from scipy import stats
@@ -29,6 +32,27 @@ def _oracle_best(w, seed):
                   max_iter=w.max_iter, pf_max=w.pf_max, seed=seed, kind=w.kind, shift=w.shift,
                   rot=w.rot, hist=w.hist)
     return p.solve()[1]
+
+
+def _host_threads():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def _oracle_bests_parallel(make, seeds, tag):
+    """The oracle's final best for every seed, the seeds spread over the
+    host's threads (each a single-threaded oracle run; ctypes releases the
+    interpreter lock during the oracle's calls)."""
+    def one(s):
+        O.set_threads(1)
+        v = _oracle_best(make(s), s)
+        print(f"[seeds] {tag} oracle seed {s}: {v:.6g}", flush=True)
+        return v
+    with ThreadPoolExecutor(max_workers=_host_threads()) as ex:
+        return list(ex.map(one, seeds))
 
 
 def _compare(gpu, ora):
@@ -75,4 +99,36 @@ def test_kapur_run_30_seeds():
         w = gen.kapur_thresholds(k=4, seed=s, pop=256, max_iter=60, img=img)
         gpu.append(_gpu_best(apo, w, "fp32", s))
         ora.append(_oracle_best(w, s))
+    _compare(gpu, ora)
+
+
+def test_rotated_fp32_full_size_30_seeds():
+    """The single large run at its full size: ps 4096, D 100, 1000
+    iterations of shifted-rotated Rastrigin in binary32 on the GPU against
+    the binary64 oracle, 30 seeds each."""
+    apo = need_gpu()
+    print("[seeds] ps4096 D100 FP32 rotated Rastrigin, 1000 iterations", flush=True)
+
+    def make(s):
+        return gen.rotated_rastrigin_large(seed=s)
+    gpu = []
+    for s in SEEDS:
+        gpu.append(_gpu_best(apo, make(s), "fp32", s))
+    print(f"[seeds] gpu bests {np.round(gpu, 2).tolist()}", flush=True)
+    ora = _oracle_bests_parallel(make, SEEDS, "c2")
+    _compare(gpu, ora)
+
+
+@pytest.mark.parametrize("k", [4, 8, 16])
+def test_kapur_full_size_30_seeds(k):
+    """The thresholding configuration at its full size: Kapur over k
+    thresholds of a 4096 x 4096 blob image, ps 1024, 500 iterations."""
+    apo = need_gpu()
+    print(f"[seeds] Kapur k={k} ps1024 T500 4096x4096 image", flush=True)
+    img = gen.blob_image(4096, 4096, seed=1)
+
+    def make(s):
+        return gen.kapur_thresholds(k=k, seed=s, img=img)
+    gpu = [_gpu_best(apo, make(s), "fp32", s) for s in SEEDS]
+    ora = _oracle_bests_parallel(make, SEEDS, f"kapur{k}")
     _compare(gpu, ora)

@@ -119,7 +119,7 @@ def test_planted_slip_is_caught(name, old, new, tmp_path):
     if cc is None:
         pytest.skip("gcc not available")
     subprocess.run([cc, "-O1", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-                    "-fno-fast-math", "-fvisibility=hidden", "-o", str(so), str(mutated), "-lm"],
+                    "-fno-fast-math", "-fvisibility=hidden", "-fopenmp", "-o", str(so), str(mutated), "-lm"],
                    check=True, capture_output=True)
     fails = P.all_failures(O.load(str(so)))
     assert fails, f"no pin detects the slip {name}"
