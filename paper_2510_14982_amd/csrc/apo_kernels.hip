@@ -30,50 +30,6 @@ constexpr int kRankPer = 8;       // protozoa ranked per workgroup
 constexpr int kRankJ = 16;        // keys per thread per pass (256 x 16 = 4096 per pass)
 
 template <typename T>
-struct RankKey;
-template <>
-struct RankKey<float> {   // 32-bit order key with the id below it: unique
-    __device__ static uint64_t make(float f, int j) {
-        return ((uint64_t)order_key(f) << 32) | (uint32_t)j;
-    }
-    __device__ static bool before(uint64_t kj, int, uint64_t ki, int) { return kj < ki; }
-};
-template <>
-struct RankKey<double> {  // 64-bit order key; equal keys fall back to the ids
-    __device__ static uint64_t make(double f, int) { return order_key(f); }
-    __device__ static bool before(uint64_t kj, int j, uint64_t ki, int i) {
-        return kj < ki || (kj == ki && j < i);
-    }
-};
-
-// Opens iteration t (one wavefront, no memory reads): pf of Eq. (11), |Dr|
-// and the Dr subset key schedule into LDS.  Lanes 0-2 draw the three Philox
-// blocks; lane 0 finishes.
-__device__ __forceinline__ void open_iteration(const Params &p, int t, uint32_t *s_keys,
-                                               int32_t *s_mdr) {
-    const int lane = threadIdx.x & 63;
-    const Stream rng = stream_of(p);
-    const Words w = rng.block(TAG_ITER, (uint32_t)(lane < 3 ? lane : 0), 0, (uint32_t)t);
-    const uint32_t u_pf = __shfl(w.w[0], 0, 64);
-    uint32_t k8[8];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        k8[e] = __shfl(w.w[e], 1, 64);
-        k8[4 + e] = __shfl(w.w[e], 2, 64);
-    }
-    if (lane == 0) {
-        const int ps = p.pop;
-        const double pf = p.pf_max * uniform<double>(u_pf);             // Eq. (11)
-        const int32_t m_dr = (int32_t)ceil((double)ps * pf);              // |Dr|
-        Subset drs;
-        subset_init(drs, k8, (uint32_t)ps);
-#pragma unroll
-        for (int q = 0; q < 24; ++q) s_keys[q] = drs.k[q];
-        *s_mdr = m_dr;
-    }
-}
-
-template <typename T>
 __device__ __forceinline__ void rank_body(const Params &p, int blk) {
     __shared__ uint64_t s_ki[kRankPer];
     __shared__ int32_t part[4][kRankPer];
@@ -456,6 +412,26 @@ hipError_t launch_rank_batch(const BatchLaunch &b, bool fp64, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_tile_persist_f32(const Params &p, int t0, int iters, hipStream_t s,
+                                   bool launch);
+hipError_t launch_tile_persist_f64(const Params &p, int t0, int iters, hipStream_t s,
+                                   bool launch);
+
+hipError_t launch_zero_u32(uint32_t *a, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_persist(const Params &p, bool fp64, int t0, int iters, hipStream_t s,
+                               bool launch) {
+    if (launch) {
+        const hipError_t e = launch_zero_u32(&p.ctrl->sync_count, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    return fp64 ? launch_tile_persist_f64(p, t0, iters, s, launch)
+                : launch_tile_persist_f32(p, t0, iters, s, launch);
+}
+
 static bool tile_form(const Params &p) {
     return p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
 }
@@ -510,7 +486,7 @@ static HistScratch hist_scratch(void *scratch) {
     return sc;
 }
 
-size_t histogram_scratch_bytes() { return histogram_out_offset() + 256 * 8; }
+size_t histogram_scratch_bytes() { return kHistScratchBytes; }
 
 static int histogram_blocks(uint64_t n) {
     const uint64_t per = (uint64_t)kHistThreads * kHistUnroll * 16;   // bytes per workgroup pass

@@ -81,6 +81,54 @@ __device__ __forceinline__ Iter load_iter(const Params &p, int init) {
 }
 
 // ---------------------------------------------------------------------------
+// Order keys of the sort and the opening of an iteration (shared by the sort
+// kernel and the persistent step).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RankKey;
+template <>
+struct RankKey<float> {   // 32-bit order key with the id below it: unique
+    __device__ static uint64_t make(float f, int j) {
+        return ((uint64_t)order_key(f) << 32) | (uint32_t)j;
+    }
+    __device__ static bool before(uint64_t kj, int, uint64_t ki, int) { return kj < ki; }
+};
+template <>
+struct RankKey<double> {  // 64-bit order key; equal keys fall back to the ids
+    __device__ static uint64_t make(double f, int) { return order_key(f); }
+    __device__ static bool before(uint64_t kj, int j, uint64_t ki, int i) {
+        return kj < ki || (kj == ki && j < i);
+    }
+};
+
+// Opens iteration t (one wavefront, no memory reads): pf of Eq. (11), |Dr|
+// and the Dr subset key schedule into LDS.  Lanes 0-2 draw the three Philox
+// blocks; lane 0 finishes.
+__device__ __forceinline__ void open_iteration(const Params &p, int t, uint32_t *s_keys,
+                                               int32_t *s_mdr) {
+    const int lane = threadIdx.x & 63;
+    const Stream rng = stream_of(p);
+    const Words w = rng.block(TAG_ITER, (uint32_t)(lane < 3 ? lane : 0), 0, (uint32_t)t);
+    const uint32_t u_pf = __shfl(w.w[0], 0, 64);
+    uint32_t k8[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        k8[e] = __shfl(w.w[e], 1, 64);
+        k8[4 + e] = __shfl(w.w[e], 2, 64);
+    }
+    if (lane == 0) {
+        const int ps = p.pop;
+        const double pf = p.pf_max * uniform<double>(u_pf);             // Eq. (11)
+        const int32_t m_dr = (int32_t)ceil((double)ps * pf);              // |Dr|
+        Subset drs;
+        subset_init(drs, k8, (uint32_t)ps);
+#pragma unroll
+        for (int q = 0; q < 24; ++q) s_keys[q] = drs.k[q];
+        *s_mdr = m_dr;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per-protozoan plan of one iteration: which operation, its mask, scalars
 // and neighbours.  Every lane of the protozoan's group computes the same
 // plan (the group shares a wavefront, so this costs no extra issue slots).
@@ -620,8 +668,12 @@ __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
 // workgroups: the choice of batches and of very large populations).
 inline int tile_rows(const Params &p) { return p.rows > 16 ? p.rows : 16; }
 
+// `itp`: the iteration and its scalars when the caller knows them (the
+// persistent form); nullptr reads them from the control block, and
+// workgroup 0 then closes the iteration there.
 template <typename T, int G, int NCH, int NPMAX, int TM>
-__device__ __forceinline__ void step_tile_body(const Params &p, int init, int blk) {
+__device__ __forceinline__ void step_tile_body(const Params &p, int init, int blk,
+                                               const Iter *itp = nullptr) {
     constexpr int NT = 512, GROUPS = NT / G, RB = TM / 16;
     static_assert(TM % 16 == 0 && TM % (NT / 32) == 0, "row blocks of 16; teams of 32 lanes");
     extern __shared__ __align__(16) unsigned char smem[];
@@ -637,7 +689,7 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
     const int zwords = TM * LZ > TM * (D + 1) ? TM * LZ : TM * (D + 1);
     T *s_p1 = Zs + zwords;    // [TM][Nt] per column-tile partial sums
     T *s_p2 = s_p1 + TM * p.Nt;
-    const Iter it = load_iter(p, init);
+    const Iter it = itp ? *itp : load_iter(p, init);
     const int t = it.t;
     const int src = (t + 1) & 1, dst = t & 1;
     const T *Xc = (const T *)p.X[src];
@@ -846,7 +898,7 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
     if (!separable) __syncthreads();
 
     // phase 4: greedy selection and the double-buffered write
-    if (!init && blk == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
+    if (!init && !itp && blk == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
     for (int row = grp; row < TM; row += GROUPS) {
         const int id = s_id[row];
         if (id < 0) continue;
