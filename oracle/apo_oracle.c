@@ -402,7 +402,9 @@ OR_EXPORT double oracle_objective(const oracle_problem *p, const double *x)
 /* Fitness order used by the sort: ascending, -0 equal to +0, NaN after */
 /* everything, equal values ordered by id.                             */
 /* ------------------------------------------------------------------ */
-static const double *g_sort_F;
+/* the array qsort's comparator reads; one per calling thread, so that
+ * concurrent calls from several host threads do not see each other's */
+static _Thread_local const double *g_sort_F;
 
 static int fitness_less(double a, int ia, double b, int ib)
 {

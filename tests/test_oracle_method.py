@@ -315,3 +315,17 @@ def test_histogram_matches_bincount():
         im = np.full((33, 7), const, np.uint8)
         h = O.histogram_u8(im)
         assert h[const] == im.size and h.sum() == im.size
+
+
+def test_rank_order_is_reentrant_across_host_threads():
+    """The sort is called from several host threads at once (seeds of the
+    distribution tests run in parallel): each call keeps its own array."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(7)
+    arrays = [rng.integers(0, 50, size=200_000).astype(np.float64) for _ in range(8)]
+    want = [np.argsort(F, kind="stable") for F in arrays]
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for _ in range(3):
+            got = list(ex.map(O.rank_order, arrays))
+            for g, w in zip(got, want):
+                assert np.array_equal(g, w)
