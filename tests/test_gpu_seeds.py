@@ -102,21 +102,21 @@ def test_kapur_run_30_seeds():
     _compare(gpu, ora)
 
 
-def test_rotated_fp32_full_size_30_seeds():
+def test_rotated_fp32_full_size_30_seeds(golden_dir):
     """The single large run at its full size: ps 4096, D 100, 1000
     iterations of shifted-rotated Rastrigin in binary32 on the GPU against
-    the binary64 oracle, 30 seeds each."""
+    the binary64 oracle, 30 seeds each.  The oracle's 30 runs (about half
+    an hour of CPU time) are read from the file tests/golden/make_seed_bests.py
+    writes with the oracle alone."""
     apo = need_gpu()
+    import json
     print("[seeds] ps4096 D100 FP32 rotated Rastrigin, 1000 iterations", flush=True)
-
-    def make(s):
-        return gen.rotated_rastrigin_large(seed=s)
-    gpu = []
-    for s in SEEDS:
-        gpu.append(_gpu_best(apo, make(s), "fp32", s))
+    with open(os.path.join(golden_dir, "seed_bests_rotated_rastrigin_ps4096_d100.json")) as f:
+        doc = json.load(f)
+    assert doc["seeds"] == list(SEEDS)
+    gpu = [_gpu_best(apo, gen.rotated_rastrigin_large(seed=s), "fp32", s) for s in SEEDS]
     print(f"[seeds] gpu bests {np.round(gpu, 2).tolist()}", flush=True)
-    ora = _oracle_bests_parallel(make, SEEDS, "c2")
-    _compare(gpu, ora)
+    _compare(gpu, doc["best_f"])
 
 
 @pytest.mark.parametrize("k", [4, 8, 16])
