@@ -203,6 +203,27 @@ int apo_time_kernels(apo_t *h, int32_t n, double *avg_us);
  * APO_E_NOMEM, APO_E_DEVICE. */
 int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint64_t *host_hist, void *stream);
 
+/* The histogram of apo_histogram_u8 for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  It calls no allocating routine: its scratch (partial
+ * counts, group rows, tickets; about 530 KB) is a file-scope device array of
+ * the library, one copy per device, held until the process ends; its device
+ * address is looked up on the first call on each device.
+ *   d_img   device [n] bytes (any alignment)
+ *   n       pixels; at most 2^32 - 1 (the scratch holds 32-bit partial
+ *           counts): larger n returns APO_E_UNSUPPORTED
+ *   d_hist  device [256] uint64 counts, 8-byte aligned (overwritten by the
+ *           kernels): count of grey level g
+ *   stream  hipStream_t the kernels run on, or NULL (null stream)
+ * Stream-ordered and asynchronous (two kernel launches, no memset node, no
+ * synchronisation), so it may be captured into a HIP graph.  Every call on a
+ * device shares that device's scratch: calls that overlap on one device
+ * (concurrent streams, or host threads) race and give wrong counts; calls
+ * ordered on one stream do not.  Counts equal apo_histogram_u8's.  Errors:
+ * APO_E_INVAL (NULL or misaligned d_hist, NULL d_img with n > 0),
+ * APO_E_UNSUPPORTED (n >= 2^32), APO_E_DEVICE (launch failure). */
+int apo_histogram_u8_noalloc(const uint8_t *d_img, uint64_t n, uint64_t *d_hist, void *stream);
+
 /* Stage times of a handle whose step runs in the GEMM form (rotated
  * objectives above 512 dimensions in binary32, and every APO_BF16 handle):
  * n more iterations (clipped like apo_run), HIP events recorded by each

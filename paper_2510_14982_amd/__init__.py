@@ -22,7 +22,7 @@ from ._lib import (APO_BF16, APO_E_DONE, APO_FLAG_PERSISTENT, APO_FLAG_PDR_PLUS,
                    OPS, APOError,
                    BatchOptions, Objective, Options, RunDesc, _check, _dptr, lib, strerror)
 
-__all__ = ["APO", "APOError", "Batch", "histogram_u8", "workspace_bytes", "lib", "strerror",
+__all__ = ["APO", "APOError", "Batch", "histogram_u8", "histogram_u8_noalloc", "workspace_bytes", "lib", "strerror",
            "OPS"]
 
 
@@ -304,4 +304,21 @@ def histogram_u8(img, stream=None) -> np.ndarray:
     _check(lib().apo_histogram_u8(C.c_void_p(img.data_ptr()), img.numel(),
                                   out.ctypes.data_as(C.POINTER(C.c_uint64)),
                                   C.c_void_p(s.cuda_stream)), "apo_histogram_u8")
+    return out
+
+
+def histogram_u8_noalloc(img, out, stream=None):
+    """The allocation-free histogram (``apo_histogram_u8_noalloc``): counts
+    of a uint8 device tensor into ``out``, a device int64/uint64 tensor of
+    256 elements; asynchronous on ``stream`` (default: the current stream)."""
+    torch = _torch()
+    if img.dtype != torch.uint8 or not img.is_cuda or not img.is_contiguous():
+        raise ValueError("histogram_u8_noalloc needs a contiguous uint8 device tensor")
+    if (not out.is_cuda or out.numel() != 256 or not out.is_contiguous()
+            or out.dtype not in (torch.int64, torch.uint64)):
+        raise ValueError("histogram_u8_noalloc needs a contiguous 256-element 64-bit device output")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().apo_histogram_u8_noalloc(C.c_void_p(img.data_ptr()), img.numel(),
+                                          C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)),
+           "apo_histogram_u8_noalloc")
     return out

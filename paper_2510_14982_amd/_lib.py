@@ -94,6 +94,8 @@ def lib():
     L.apo_time_kernels.argtypes = [vp, i32, P(d)]
     L.apo_histogram_u8.restype = C.c_int
     L.apo_histogram_u8.argtypes = [vp, u64, vp, vp]
+    L.apo_histogram_u8_noalloc.restype = C.c_int
+    L.apo_histogram_u8_noalloc.argtypes = [vp, u64, vp, vp]
     L.apo_batch_workspace_bytes.restype = C.c_size_t
     L.apo_batch_workspace_bytes.argtypes = [i32, P(RunDesc)]
     L.apo_batch_create.restype = C.c_int

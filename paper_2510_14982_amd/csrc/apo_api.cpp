@@ -1098,6 +1098,15 @@ int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint64_t *host_hist, void
     return ok ? APO_OK : APO_E_DEVICE;
 }
 
+int apo_histogram_u8_noalloc(const uint8_t *d_img, uint64_t n, uint64_t *d_hist, void *stream) {
+    if (!d_hist || ((uintptr_t)d_hist & 7u) != 0 || (!d_img && n > 0)) return APO_E_INVAL;
+    if (n >= (1ull << 32)) return APO_E_UNSUPPORTED;
+    return apok::launch_histogram_noalloc(d_img, n, (unsigned long long *)d_hist,
+                                          (hipStream_t)stream) == hipSuccess
+               ? APO_OK
+               : APO_E_DEVICE;
+}
+
 size_t apo_batch_workspace_bytes(int32_t n, const apo_run_desc *runs) {
     BatchLayout B;
     return batch_layout(n, runs, B) == APO_OK ? B.total : 0;

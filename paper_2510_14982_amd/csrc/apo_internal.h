@@ -128,6 +128,11 @@ constexpr size_t kHistScratchBytes = histogram_out_offset() + 256 * 8;
 size_t histogram_scratch_bytes();
 
 hipError_t launch_histogram(const uint8_t *img, uint64_t n, void *scratch, hipStream_t s);
+// The same histogram with the device's file-scope scratch array instead of
+// a caller buffer, the counts written to d_out (device [256] uint64).  No
+// allocation; calls that overlap on one device race on the shared scratch.
+hipError_t launch_histogram_noalloc(const uint8_t *img, uint64_t n, unsigned long long *d_out,
+                                    hipStream_t s);
 
 // The GEMM form of one step (or of the initial evaluation), and the binary64
 // re-score of one row x (device, binary64) into out[0].

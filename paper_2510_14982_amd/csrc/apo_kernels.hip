@@ -11,6 +11,8 @@
 //   hist_kernel   256-bin histogram of an 8-bit image, per-wave LDS copies.
 #include "apo_step.hpp"
 
+#include <mutex>
+
 namespace apok {
 
 // ---------------------------------------------------------------------------
@@ -496,8 +498,8 @@ static int histogram_blocks(uint64_t n) {
     return (int)blocks;
 }
 
-hipError_t launch_histogram(const uint8_t *img, uint64_t n, void *scratch, hipStream_t s) {
-    const HistScratch sc = hist_scratch(scratch);
+static hipError_t launch_histogram_sc(const uint8_t *img, uint64_t n, const HistScratch &sc,
+                                      hipStream_t s) {
     // the tickets start at zero (a fill kernel, not a memset node)
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, sc.tickets, kHistGroups + 1);
     hipError_t e = hipGetLastError();
@@ -505,6 +507,49 @@ hipError_t launch_histogram(const uint8_t *img, uint64_t n, void *scratch, hipSt
     hipLaunchKernelGGL(hist_kernel, dim3((unsigned)histogram_blocks(n)), dim3(kHistThreads), 0,
                        s, img, n, sc);
     return hipGetLastError();
+}
+
+hipError_t launch_histogram(const uint8_t *img, uint64_t n, void *scratch, hipStream_t s) {
+    return launch_histogram_sc(img, n, hist_scratch(scratch), s);
+}
+
+// The histogram's scratch for callers that cannot allocate: one file-scope
+// array per device, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address of each GPU's copy is looked up once, with
+// that GPU current, and kept per device.  Every call on a GPU uses that
+// GPU's copy, so calls that overlap on one GPU race.
+__device__ __align__(256) unsigned char scratch[kHistScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static hipError_t scratch_of_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_histogram_noalloc(const uint8_t *img, uint64_t n, unsigned long long *d_out,
+                                    hipStream_t s) {
+    void *ptr = nullptr;
+    const hipError_t e = scratch_of_current_device(&ptr);
+    if (e != hipSuccess) return e;
+    HistScratch sc = hist_scratch(ptr);
+    sc.out = d_out;   // the counts go straight to the caller's buffer
+    return launch_histogram_sc(img, n, sc, s);
 }
 
 }  // namespace apok
