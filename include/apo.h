@@ -80,12 +80,9 @@ typedef struct {
 
 enum {
     APO_FLAG_TRACE = 1u,      /* keep every candidate of the last step for apo_get_trace */
-    APO_FLAG_PDR_PLUS = 2u,   /* Eq. (13) with the opposite sign before the cosine (a
+    APO_FLAG_PDR_PLUS = 2u    /* Eq. (13) with the opposite sign before the cosine (a
                                  variant of the printed formula: the worst ranks of Dr,
                                  not the best, are the likeliest to go dormant)       */
-    APO_FLAG_PERSISTENT = 4u  /* apo_run runs its iterations in the persistent form
-                                 where the handle allows it (see apo_run); same
-                                 results as the graph-replayed form                */
 };
 
 typedef struct {
@@ -141,14 +138,7 @@ int apo_step(apo_t *h);
  * executed (>= 0) or a status.  The sort and step kernels of each iteration
  * are replayed from HIP graphs, captured on the first call (apo_run(h, 0)
  * captures them and executes nothing, so a later timed call does not
- * include the capture).  Handles created with APO_FLAG_PERSISTENT whose
- * step is tiled (rotated objectives below the GEMM form, thresholds), with
- * tiles of at most 32 rows and a grid that fits on the device at once, run
- * all iterations in one cooperative launch instead (the persistent form:
- * sort and step of every iteration separated by grid barriers); both forms
- * compute the same results.  A persistent launch whose grid barrier gives
- * up (bounded wait) is reported as APO_E_DEVICE by the next call that
- * synchronises (apo_best, apo_get_state, apo_get_trace). */
+ * include the capture). */
 int apo_run(apo_t *h, int32_t iters);
 
 /* The best protozoan (lowest fitness; NaN never wins; lowest id on ties):
@@ -184,10 +174,7 @@ int apo_get_trace(apo_t *h, double *Y, double *Fy, int32_t *op, int32_t *perm);
  * measured with HIP events that each launch records itself at the kernel's
  * start and end (kernel execution alone, launch gaps excluded):
  * avg_us[0] rank sort, avg_us[1] step (update + evaluation + selection).
- * A handle in the persistent form times one launch of n iterations between
- * two events on its stream: avg_us[0] = 0 (the sort runs inside) and
- * avg_us[1] = the launch's time per iteration.  Returns the number of
- * iterations executed or a status. */
+ * Returns the number of iterations executed or a status. */
 int apo_time_kernels(apo_t *h, int32_t n, double *avg_us);
 
 /* 256-bin grey-level histogram of an 8-bit image (the input of the Kapur and

@@ -16,7 +16,7 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import (APO_BF16, APO_E_DONE, APO_FLAG_PERSISTENT, APO_FLAG_PDR_PLUS, APO_FLAG_TRACE,
+from ._lib import (APO_BF16, APO_E_DONE, APO_FLAG_PDR_PLUS, APO_FLAG_TRACE,
                    APO_FP32, APO_FP64,
                    KINDS,
                    OPS, APOError,
@@ -65,14 +65,13 @@ class APO:
     np_pairs, pf_max, seed, max_iter, precision ("fp64" | "fp32"), objective
     kind and its inputs (shift [dim], rot [dim, dim] row-major, hist [256]).
     ``trace=True`` keeps every candidate of the last step for
-    ``get_trace``; ``persistent=True`` lets ``run`` use the persistent form
-    (all iterations in one cooperative launch) where the handle allows it.  The workspace is a torch uint8 tensor on the current
+    ``get_trace``.  The workspace is a torch uint8 tensor on the current
     device and launches go to ``stream`` (default: torch's current stream).
     """
 
     def __init__(self, dim, lb, ub, pop, np_pairs=1, pf_max=0.1, seed=1, max_iter=100,
                  precision="fp64", kind="sphere", shift=None, rot=None, hist=None, run_id=0,
-                 trace=False, stream=None, pdr_plus=False, persistent=False):
+                 trace=False, stream=None, pdr_plus=False):
         torch = _torch()
         self.dim, self.pop, self.max_iter = int(dim), int(pop), int(max_iter)
         self.precision = precision
@@ -81,8 +80,7 @@ class APO:
         shift = None if shift is None else np.ascontiguousarray(shift, np.float64).reshape(self.dim)
         rot = None if rot is None else np.ascontiguousarray(rot, np.float64).reshape(self.dim, self.dim)
         hist = None if hist is None else np.ascontiguousarray(hist, np.uint64).reshape(256)
-        flags = (APO_FLAG_TRACE if trace else 0) | (APO_FLAG_PDR_PLUS if pdr_plus else 0) | \
-            (APO_FLAG_PERSISTENT if persistent else 0)
+        flags = (APO_FLAG_TRACE if trace else 0) | (APO_FLAG_PDR_PLUS if pdr_plus else 0)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         o = _options(max_iter, precision, kind, shift, rot, hist, run_id, flags)
         nbytes = int(lib().apo_workspace_bytes(self.dim, self.pop, C.byref(o)))

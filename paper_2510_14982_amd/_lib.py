@@ -21,7 +21,6 @@ APO_FP64, APO_FP32, APO_BF16 = 0, 1, 2
 KINDS = {"sphere": 0, "rastrigin": 1, "rosenbrock": 2, "ackley": 3, "kapur": 4, "otsu": 5}
 APO_FLAG_TRACE = 1
 APO_FLAG_PDR_PLUS = 2
-APO_FLAG_PERSISTENT = 4
 OPS = {0: "dormancy", 1: "reproduction", 2: "autotroph", 3: "heterotroph"}
 
 

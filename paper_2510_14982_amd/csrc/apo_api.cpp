@@ -217,8 +217,6 @@ struct apo {
     hipEvent_t ev[4];
     bool have_events;
     bool batch_view;      // a member of a batch: stepped only through the batch
-    bool persist;         // apo_run uses the persistent form (one cooperative launch)
-    bool persist_launched;   // a persistent launch may have recorded a barrier failure
 };
 
 #define APO_HIP(h, call)                       \
@@ -231,7 +229,6 @@ struct apo {
 
 
 static int destroy_impl(apo_t *h);
-static int persist_check(apo_t *h);
 
 // ---------------------------------------------------------------------------
 // Batches of runs.  Each member is an ordinary handle whose workspace is a
@@ -745,9 +742,6 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     CREATE_HIP(apok::launch_init(p, h->fp64, s));
     CREATE_HIP(hipStreamSynchronize(s));   // host staging buffers go out of scope
 #undef CREATE_HIP
-    // the persistent form: tiled steps whose whole grid fits on the device
-    if ((opt->flags & APO_FLAG_PERSISTENT) && !gf && (p.rotated || is_threshold(p.kind)))
-        h->persist = apok::launch_tile_persist(p, h->fp64, 0, 0, s, false) == hipSuccess;
     (void)hipGetLastError();
     h->t = 0;
     *out = h;
@@ -813,13 +807,6 @@ int apo_run(apo_t *h, int32_t iters) {
     if (h->poisoned) return APO_E_DEVICE;
     int32_t n = h->T - h->t;
     if (iters < n) n = iters;
-    if (h->persist) {   // all n iterations in one cooperative launch
-        if (n <= 0) return 0;
-        APO_HIP(h, apok::launch_tile_persist(h->p, h->fp64, h->t, n, h->stream, true));
-        h->persist_launched = true;
-        h->t += n;
-        return n;
-    }
     if (!h->graph_tried) {   // apo_run(h, 0) only does this
         h->graph_tried = true;
         capture_iterations(h, 1, &h->graph[0], &h->graph_exec[0]);
@@ -857,24 +844,6 @@ int apo_time_kernels(apo_t *h, int32_t iters, double *avg_us) {
     if (!h->have_events) {
         for (int i = 0; i < 4; ++i) APO_HIP(h, hipEventCreate(&h->ev[i]));
         h->have_events = true;
-    }
-    if (h->persist) {
-        // one launch of n iterations between two events on the stream
-        // (the barrier counter's fill kernel included): [0] 0, the sort
-        // runs inside; [1] the persistent kernel per iteration
-        APO_HIP(h, hipEventRecord(h->ev[2], h->stream));
-        APO_HIP(h, apok::launch_tile_persist(h->p, h->fp64, h->t, n, h->stream, true));
-        APO_HIP(h, hipEventRecord(h->ev[3], h->stream));
-        h->persist_launched = true;
-        APO_HIP(h, hipEventSynchronize(h->ev[3]));
-        float ms = 0.f;
-        APO_HIP(h, hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
-        h->t += n;
-        const int rc = persist_check(h);
-        if (rc != APO_OK) return rc;
-        avg_us[0] = 0.0;
-        avg_us[1] = 1000.0 * ms / n;
-        return n;
     }
     // each launch records its own start and end events (kernel execution
     // alone, as a kernel trace measures it)
@@ -970,28 +939,9 @@ int apo_info(const apo_t *h, int32_t *iter, int64_t *fes) {
     return h->poisoned ? APO_E_DEVICE : APO_OK;
 }
 
-// After a persistent launch: whether a grid barrier gave up (the launch then
-// stopped early and the state is not an iteration's).  Synchronises.
-static int persist_check(apo_t *h) {
-    if (!h->persist_launched) return APO_OK;
-    int32_t err = 0;
-    APO_HIP(h, hipMemcpyAsync(&err, &h->p.ctrl->sync_err, 4, hipMemcpyDeviceToHost, h->stream));
-    APO_HIP(h, hipStreamSynchronize(h->stream));
-    if (err != 0) {
-        h->poisoned = true;
-        return APO_E_DEVICE;
-    }
-    h->persist_launched = false;
-    return APO_OK;
-}
-
 int apo_best(apo_t *h, double *x_out, double *f_out, int64_t *fes_out) {
     if (!h) return APO_E_INVAL;
     if (h->poisoned) return APO_E_DEVICE;
-    {
-        const int rc = persist_check(h);
-        if (rc != APO_OK) return rc;
-    }
     double *d_best = (double *)(h->ws + h->L.best);
     std::vector<double> row((size_t)h->dim + 1);
     APO_HIP(h, apok::launch_best(h->p, h->fp64, h->t & 1, d_best, h->stream));
@@ -1019,10 +969,6 @@ static int copy_rows_out(apo_t *h, const void *dev, double *host, int rows, int 
 int apo_get_state(apo_t *h, double *X, double *F, int32_t *iter) {
     if (!h) return APO_E_INVAL;
     if (h->poisoned) return APO_E_DEVICE;
-    {
-        const int rc = persist_check(h);
-        if (rc != APO_OK) return rc;
-    }
     const int cur = h->t & 1;
     if (X) {
         const int rc = copy_rows_out(h, h->p.X[cur], X, h->pop, h->dim, h->L.Dp);
@@ -1065,10 +1011,6 @@ int apo_set_state(apo_t *h, const double *X, const double *F, int32_t iter) {
 int apo_get_trace(apo_t *h, double *Y, double *Fy, int32_t *op, int32_t *perm) {
     if (!h) return APO_E_INVAL;
     if (h->poisoned) return APO_E_DEVICE;
-    {
-        const int rc = persist_check(h);
-        if (rc != APO_OK) return rc;
-    }
     if (!h->p.trace) return APO_E_STATE;
     if (Y) {
         const int rc = copy_rows_out(h, h->p.trY, Y, h->pop, h->dim, h->L.Dp);

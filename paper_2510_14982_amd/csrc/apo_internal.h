@@ -25,9 +25,7 @@ struct Ctrl {
     int32_t best_id;      // written by the best kernel
     double best_f;
     double p_ah, fscale, cnear;   // Eqs. (12), (4), (9) at t_next
-    uint32_t sync_count;  // grid barriers of the persistent form (zero at each launch)
-    int32_t sync_err;     // nonzero: a persistent launch gave up on a barrier
-    int32_t pad[46];
+    int32_t pad[48];
 };
 
 // Buffers of the GEMM form (rotated objectives of large dimension, and the
@@ -138,12 +136,6 @@ hipError_t launch_histogram_noalloc(const uint8_t *img, uint64_t n, unsigned lon
 // re-score of one row x (device, binary64) into out[0].
 hipError_t launch_gemm_step(const Params &p, const GemmBufs &w, int init, hipStream_t s);
 
-// The persistent form of the tiled step (single handles): iterations
-// t0 + 1 .. t0 + iters in one cooperative launch, after clearing the barrier
-// counter.  With launch == false only checks that the grid fits on the
-// device at once (hipSuccess) or not (hipErrorCooperativeLaunchTooLarge).
-hipError_t launch_tile_persist(const Params &p, bool fp64, int t0, int iters, hipStream_t s,
-                               bool launch);
 hipError_t launch_zero_u32(uint32_t *a, int n, hipStream_t s);
 // One stage of it: 0 candidates, 1 product (BF16 estimate or binary32),
 // 2 BF16 classification, 3 binary32 re-score product, 4 selection.

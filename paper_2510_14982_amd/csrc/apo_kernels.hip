@@ -414,24 +414,9 @@ hipError_t launch_rank_batch(const BatchLaunch &b, bool fp64, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tile_persist_f32(const Params &p, int t0, int iters, hipStream_t s,
-                                   bool launch);
-hipError_t launch_tile_persist_f64(const Params &p, int t0, int iters, hipStream_t s,
-                                   bool launch);
-
 hipError_t launch_zero_u32(uint32_t *a, int n, hipStream_t s) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, n);
     return hipGetLastError();
-}
-
-hipError_t launch_tile_persist(const Params &p, bool fp64, int t0, int iters, hipStream_t s,
-                               bool launch) {
-    if (launch) {
-        const hipError_t e = launch_zero_u32(&p.ctrl->sync_count, 1, s);
-        if (e != hipSuccess) return e;
-    }
-    return fp64 ? launch_tile_persist_f64(p, t0, iters, s, launch)
-                : launch_tile_persist_f32(p, t0, iters, s, launch);
 }
 
 static bool tile_form(const Params &p) {

@@ -82,7 +82,7 @@ __device__ __forceinline__ Iter load_iter(const Params &p, int init) {
 
 // ---------------------------------------------------------------------------
 // Order keys of the sort and the opening of an iteration (shared by the sort
-// kernel and the persistent step).
+// kernel and the step).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct RankKey;
@@ -668,9 +668,9 @@ __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
 // workgroups: the choice of batches and of very large populations).
 inline int tile_rows(const Params &p) { return p.rows > 16 ? p.rows : 16; }
 
-// `itp`: the iteration and its scalars when the caller knows them (the
-// persistent form); nullptr reads them from the control block, and
-// workgroup 0 then closes the iteration there.
+// `itp`: the iteration and its scalars when the caller knows them; nullptr
+// reads them from the control block, and workgroup 0 then closes the
+// iteration there.
 template <typename T, int G, int NCH, int NPMAX, int TM>
 __device__ __forceinline__ void step_tile_body(const Params &p, int init, int blk,
                                                const Iter *itp = nullptr) {
