@@ -148,15 +148,58 @@ hipError_t launch_elite_f64(const Params &p, const GemmBufs &w, const double *x,
 // (step_shape), one rank launch per precision.
 hipError_t launch_rank_batch(const BatchLaunch &b, bool fp64, hipStream_t s);
 hipError_t launch_step_batch(const Params &proto, bool fp64, const BatchLaunch &b, hipStream_t s);
-int rank_blocks(const Params &p);              // workgroups of a run's sort
-int step_blocks(const Params &p);              // workgroups of a run's step
-size_t step_lds_bytes(const Params &p, bool fp64);
-int step_shape(const Params &p, bool fp64);    // equal iff one kernel serves both runs
+// Launch geometry of a run (host side; shared by the runtime, the launchers
+// and the CPU checks of the batch tables).
 
 // The tiled step's lanes per protozoan and chunks per lane for a run (its
 // own lane count when set, else the dimension's); -1 chunks if none fits.
-int tile_lanes(const Params &p);
-int tile_chunks(const Params &p);
+inline int tile_lanes(const Params &p) { return p.lanes > 0 ? p.lanes : lanes_for_dim(p.dim); }
+inline int tile_chunks(const Params &p) { return chunks_for(p.dim, tile_lanes(p)); }
+
+// Rows (consecutive ranks) per workgroup of the tiled step: one MFMA row
+// block of 16, or "wide" -- one row per lane group of the 512 threads --
+// which fills every thread when the lane groups are small (fewer, fuller
+// workgroups: the choice of batches and of very large populations).
+inline int tile_rows(const Params &p) { return p.rows > 16 ? p.rows : 16; }
+
+// The tiled step serves rotated objectives and the thresholding objectives.
+inline bool tile_form(const Params &p) {
+    return p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
+}
+
+inline size_t tile_lds_bytes(const Params &p, bool fp64) {
+    return tile_dynamic_lds(p.dim, tile_rows(p), fp64 ? 8 : 4);
+}
+
+// Protozoa ranked per workgroup of the register form of the sort.
+constexpr int kRankPer = 8;
+
+// Workgroups of a run's sort: 256 protozoa each in the LDS form, kRankPer
+// in the register form.
+inline int rank_blocks(const Params &p) {
+    return p.rank_lds ? (p.pop + 255) / 256 : (p.pop + kRankPer - 1) / kRankPer;
+}
+
+// Workgroups of a run's step.
+inline int step_blocks(const Params &p) {
+    if (tile_form(p)) return (p.pop + tile_rows(p) - 1) / tile_rows(p);
+    return (int)(((long long)p.pop * lanes_for_dim(p.dim) + 255) / 256);
+}
+
+// Dynamic LDS of a run's step launch.
+inline size_t step_lds_bytes(const Params &p, bool fp64) {
+    return tile_form(p) ? tile_lds_bytes(p, fp64) : 0;
+}
+
+// Instantiation key: precision, form, lanes, chunks, rows and whether np > 1
+// (equal keys: one kernel serves both runs).
+inline int step_shape(const Params &p, bool fp64) {
+    return tile_form(p) ? pack_shape(fp64, true, p.np > 1, tile_lanes(p), tile_chunks(p),
+                                     tile_rows(p))
+                        : pack_shape(fp64, false, p.np > 1, lanes_for_dim(p.dim),
+                                     chunks_for_dim(p.dim), 0);
+}
+
 // Largest population the LDS form of the sort takes.
 constexpr int kRankLdsMax = 1024;
 

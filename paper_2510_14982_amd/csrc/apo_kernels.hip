@@ -28,7 +28,6 @@ namespace apok {
 // of F) and whether the rank is in Dr.  Workgroup 0 publishes the
 // iteration in the control block.
 // ---------------------------------------------------------------------------
-constexpr int kRankPer = 8;       // protozoa ranked per workgroup
 constexpr int kRankJ = 16;        // keys per thread per pass (256 x 16 = 4096 per pass)
 
 template <typename T>
@@ -368,9 +367,6 @@ __global__ __launch_bounds__(kHistThreads) void hist_kernel(const uint8_t *img, 
 // ---------------------------------------------------------------------------
 // Host-side launch selection.
 // ---------------------------------------------------------------------------
-int tile_lanes(const Params &p) { return p.lanes > 0 ? p.lanes : lanes_for_dim(p.dim); }
-
-int tile_chunks(const Params &p) { return chunks_for(p.dim, tile_lanes(p)); }
 
 hipError_t launch_elem_f32(const Params &p, int init, hipStream_t s);
 hipError_t launch_elem_f64(const Params &p, int init, hipStream_t s);
@@ -419,9 +415,6 @@ hipError_t launch_zero_u32(uint32_t *a, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-static bool tile_form(const Params &p) {
-    return p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
-}
 
 hipError_t launch_step_batch(const Params &proto, bool fp64, const BatchLaunch &b, hipStream_t s) {
     if (tile_form(proto))
@@ -429,25 +422,9 @@ hipError_t launch_step_batch(const Params &proto, bool fp64, const BatchLaunch &
     return fp64 ? launch_elem_batch_f64(proto, b, s) : launch_elem_batch_f32(proto, b, s);
 }
 
-int rank_blocks(const Params &p) {
-    return p.rank_lds ? (p.pop + 255) / 256 : (p.pop + kRankPer - 1) / kRankPer;
-}
 
-int step_blocks(const Params &p) {
-    if (tile_form(p)) return (p.pop + tile_rows(p) - 1) / tile_rows(p);
-    return (int)(((long long)p.pop * lanes_for_dim(p.dim) + 255) / 256);
-}
 
-size_t step_lds_bytes(const Params &p, bool fp64) {
-    return tile_form(p) ? tile_lds_bytes(p, fp64) : 0;
-}
 
-// Instantiation key: precision, form, lanes, chunks, rows and whether np > 1.
-int step_shape(const Params &p, bool fp64) {
-    const bool tf = tile_form(p);
-    return tf ? pack_shape(fp64, true, p.np > 1, tile_lanes(p), tile_chunks(p), tile_rows(p))
-              : pack_shape(fp64, false, p.np > 1, lanes_for_dim(p.dim), chunks_for_dim(p.dim), 0);
-}
 
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s) {
     if (fp64)

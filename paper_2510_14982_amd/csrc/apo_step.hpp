@@ -662,11 +662,6 @@ __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
     return tile_row_stride(p.Dp, p.Ks, es);
 }
 
-// Rows (consecutive ranks) per workgroup of the tiled step: one MFMA row
-// block of 16, or "wide" -- one row per lane group of the 512 threads --
-// which fills every thread when the lane groups are small (fewer, fuller
-// workgroups: the choice of batches and of very large populations).
-inline int tile_rows(const Params &p) { return p.rows > 16 ? p.rows : 16; }
 
 // `itp`: the iteration and its scalars when the caller knows them; nullptr
 // reads them from the control block, and workgroup 0 then closes the
@@ -950,13 +945,6 @@ __global__ __launch_bounds__(512) void step_tile_batch(const Params *runs, const
     step_tile_body<T, G, NCH, NPMAX, TM>(runs[b.x], init, b.y);
 }
 
-inline bool use_tile(const Params &p) {
-    return p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
-}
-
-inline size_t tile_lds_bytes(const Params &p, bool fp64) {
-    return tile_dynamic_lds(p.dim, tile_rows(p), fp64 ? 8 : 4);
-}
 
 // A launch of one handle (b == nullptr: grid of the run's own blocks, lds
 // from its shape) or of a batch (b: the runs of one kernel shape, `p` one
