@@ -183,7 +183,7 @@ int apo_time_kernels(apo_t *h, int32_t n, double *avg_us);
  *   n          pixels, n < 2^32
  *   host_hist  host [256] uint64 counts (overwritten): count of grey level g
  *   stream     hipStream_t the kernels run on, or NULL (null stream)
- * Allocates a device scratch buffer of about 530 KB for the call (partial
+ * Allocates a device scratch buffer of about 514 KB for the call (partial
  * counts), runs the histogram kernel and copies the counts to the host;
  * synchronises the stream before returning.  Counts are exact.  Errors:
  * APO_E_INVAL (NULL host_hist, NULL d_img with n > 0, n >= 2^32),
@@ -193,7 +193,7 @@ int apo_histogram_u8(const uint8_t *d_img, uint64_t n, uint64_t *host_hist, void
 /* The histogram of apo_histogram_u8 for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  It calls no allocating routine: its scratch (partial
- * counts, group rows, tickets; about 530 KB) is a file-scope device array of
+ * counts; about 514 KB) is a file-scope device array of
  * the library, one copy per device, held until the process ends; its device
  * address is looked up on the first call on each device.
  *   d_img   device [n] bytes (any alignment)

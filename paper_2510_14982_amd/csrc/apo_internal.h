@@ -117,11 +117,10 @@ hipError_t launch_step(const Params &p, bool fp64, hipStream_t s);
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s);
 hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream_t s);
 // 256-bin histogram of n bytes into scratch (histogram_scratch_bytes():
-// per-workgroup partial rows, group rows, tickets, then the 256 uint64
-// counts at byte offset histogram_out_offset()).  Stream-ordered, no
-// allocation.
+// per-workgroup partial rows, then the 256 uint64 counts at byte offset
+// histogram_out_offset()).  Stream-ordered (two launches), no allocation.
 constexpr int kHistBlocks = 512;   // workgroups of the image pass at most
-constexpr size_t histogram_out_offset() { return ((size_t)(kHistBlocks + 16) * 256 + 64) * 4; }
+constexpr size_t histogram_out_offset() { return (size_t)kHistBlocks * 256 * 4; }
 constexpr size_t kHistScratchBytes = histogram_out_offset() + 256 * 8;
 size_t histogram_scratch_bytes();
 

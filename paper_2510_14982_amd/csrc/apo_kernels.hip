@@ -8,7 +8,9 @@
 //                 flags the ranks in Dr.
 //   (the step kernels themselves live in apo_step.hpp)
 //   best_kernel   argmin in the fitness order and a copy of that row.
-//   hist_kernel   256-bin histogram of an 8-bit image, per-wave LDS copies.
+//   hist_count_kernel, hist_sum_kernel
+//                 256-bin histogram of an 8-bit image (LDS copies per
+//                 workgroup, then one workgroup adds the workgroups' rows).
 #include "apo_step.hpp"
 
 #include <mutex>
@@ -239,21 +241,44 @@ __global__ __launch_bounds__(1024) void best_kernel(Params p, int cur, double *o
 }
 
 // ---------------------------------------------------------------------------
-// Histogram tables for the thresholding objectives (one thread, binary64,
-// bins in order): P[g] = sum_{h<g} p_h, S[g] = sum_{h<g} p_h ln p_h,
-// M1[g] = sum_{h<g} h p_h, with p_h = count_h / N.
+// Histogram tables for the thresholding objectives (binary64, bins in
+// order): P[g] = sum_{h<g} p_h, S[g] = sum_{h<g} p_h ln p_h,
+// M1[g] = sum_{h<g} h p_h, with p_h = count_h / N.  One workgroup of 256
+// threads: each loads one count and forms its bin's terms; N is the exact
+// integer total; one thread then adds the terms in bin order.
 // ---------------------------------------------------------------------------
-__global__ void hist_tables_kernel(const uint64_t *hist, double *tab) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double N = 0.0;
-    for (int g = 0; g < 256; ++g) N += (double)hist[g];
-    double *P = tab, *S = tab + 257, *M1 = tab + 514;
-    P[0] = S[0] = M1[0] = 0.0;
-    for (int g = 0; g < 256; ++g) {
-        const double pg = (double)hist[g] / N;
-        P[g + 1] = P[g] + pg;
-        S[g + 1] = S[g] + (pg > 0.0 ? pg * log(pg) : 0.0);
-        M1[g + 1] = M1[g] + (double)g * pg;
+__global__ __launch_bounds__(256) void hist_tables_kernel(const uint64_t *hist, double *tab) {
+    __shared__ unsigned long long s_c[256];
+    __shared__ double s_p[256], s_s[256], s_m[256];
+    const int g = threadIdx.x;
+    const unsigned long long c = hist[g];
+    s_c[g] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {   // exact: integers
+        unsigned long long v = 0;
+        if (g < h) v = s_c[g] + s_c[g + h];
+        __syncthreads();
+        if (g < h) s_c[g] = v;
+        __syncthreads();
+    }
+    const double N = (double)s_c[0];
+    const double pg = (double)c / N;
+    s_p[g] = pg;
+    s_s[g] = pg > 0.0 ? pg * log(pg) : 0.0;
+    s_m[g] = (double)g * pg;
+    __syncthreads();
+    if (g == 0) {
+        double *P = tab, *S = tab + 257, *M1 = tab + 514;
+        double a = 0.0, b = 0.0, m = 0.0;
+        P[0] = S[0] = M1[0] = 0.0;
+        for (int q = 0; q < 256; ++q) {
+            a = a + s_p[q];
+            b = b + s_s[q];
+            m = m + s_m[q];
+            P[q + 1] = a;
+            S[q + 1] = b;
+            M1[q + 1] = m;
+        }
     }
 }
 
@@ -262,28 +287,31 @@ __global__ void zero_u32_kernel(uint32_t *a, int n) {
     if (i < n) a[i] = 0u;
 }
 
-// 8-bit histogram.  Each workgroup of 512 threads counts its share of the
-// image into LDS: sixteen copies chosen by lane % 16, so lanes that meet the
-// same grey level (frequent in images made of uniform regions) mostly hit
-// different copies; copies are 257 words apart so equal levels of different
-// copies sit in different banks.  Bytes before the first and after the last
-// 16-byte boundary are counted one by one; the rest is read as 16-byte
-// vectors, four per thread in flight.  The 256 counts go to the
-// workgroup's row of the partial table (no global atomics on the bins),
-// which is summed by a two-level ticket tree: the last workgroup of each of
-// up to 16 groups (a device-scope ticket per group) sums the group's rows
-// into a group row, and the last group to finish sums the group rows into
-// the 64-bit output.  Every sum runs in a fixed order.
+// 8-bit histogram, two kernels.  hist_count: each workgroup of 512 threads
+// counts its share of the image into LDS: sixteen copies chosen by
+// lane % 16, so lanes that meet the same grey level (frequent in images
+// made of uniform regions) mostly hit different copies; copies are 257
+// words apart so equal levels of different copies sit in different banks.
+// Bytes before the first and after the last 16-byte boundary are counted
+// one by one; the rest is read as 16-byte vectors, four per thread in
+// flight.  The 256 counts go to the workgroup's row of the partial table.
+// Workgroup 0 of the counting pass also clears the 64-bit output.
+// hist_sum: workgroup j (of ceil(rows / 32)) adds rows j, j + grid, ...,
+// one thread per bin with its 32 loads in flight together, and adds that
+// to the output with one 64-bit atomic per bin.  The kernel boundary
+// between the two publishes the rows and the cleared output:
+// no workgroup of the counting pass waits on another or fences its writes
+// (a device-scope release writes back the whole L2 of its XCD, and one per
+// workgroup costs more than the counting).  Integer sums: exact in any
+// order.
 constexpr int kHistCopies = 16;
 constexpr int kHistStride = 257;
 constexpr int kHistThreads = 512;
-constexpr int kHistGroups = 16;
 constexpr int kHistUnroll = 4;
+constexpr int kHistSumBatch = 32;   // rows per thread of the sum, loaded together
 
 struct HistScratch {
     uint32_t *rows;                // [kHistBlocks][256]
-    uint32_t *group_rows;          // [kHistGroups][256]
-    uint32_t *tickets;             // [kHistGroups + 1]
     unsigned long long *out;       // [256]
 };
 
@@ -296,10 +324,11 @@ __device__ __forceinline__ void hist_add16(uint32_t *mine, const uint4 &q) {
     }
 }
 
-__global__ __launch_bounds__(kHistThreads) void hist_kernel(const uint8_t *img, uint64_t n,
-                                                            HistScratch sc) {
+__global__ __launch_bounds__(kHistThreads) void hist_count_kernel(const uint8_t *img, uint64_t n,
+                                                                  uint32_t *rows,
+                                                                  unsigned long long *out) {
     __shared__ uint32_t h[kHistCopies * kHistStride];
-    __shared__ bool last;
+    if (blockIdx.x == 0 && threadIdx.x < 256) out[threadIdx.x] = 0ull;
     uint32_t *mine = h + (threadIdx.x & (kHistCopies - 1)) * kHistStride;
     for (int b = threadIdx.x; b < kHistCopies * kHistStride; b += kHistThreads) h[b] = 0u;
     __syncthreads();
@@ -328,40 +357,23 @@ __global__ __launch_bounds__(kHistThreads) void hist_kernel(const uint8_t *img, 
         uint32_t s = 0;
 #pragma unroll
         for (int c = 0; c < kHistCopies; ++c) s += h[c * kHistStride + b];
-        sc.rows[(size_t)blockIdx.x * 256 + b] = s;
+        rows[(size_t)blockIdx.x * 256 + b] = s;
     }
-    // level 1: the last workgroup of this group sums the group's rows
-    const unsigned nb = gridDim.x;
-    const unsigned per = (nb + kHistGroups - 1) / kHistGroups;
-    const unsigned ngroups = (nb + per - 1) / per;
-    const unsigned g = blockIdx.x / per, r0 = g * per, r1 = r0 + per < nb ? r0 + per : nb;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&sc.tickets[g], 1u) == r1 - r0 - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (b < 256) {
-        uint32_t s = 0;
-        for (unsigned r = r0; r < r1; ++r)
-            s += __hip_atomic_load(&sc.rows[(size_t)r * 256 + b], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        sc.group_rows[(size_t)g * 256 + b] = s;
+}
+
+__global__ __launch_bounds__(256) void hist_sum_kernel(const uint32_t *rows, int nb,
+                                                       unsigned long long *out) {
+    const int bin = threadIdx.x;
+    uint32_t v[kHistSumBatch];
+#pragma unroll
+    for (int u = 0; u < kHistSumBatch; ++u) {
+        const int r = (int)blockIdx.x + (int)gridDim.x * u;
+        v[u] = r < nb ? rows[(size_t)r * 256 + bin] : 0u;
     }
-    // level 2: the last group sums the group rows
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&sc.tickets[kHistGroups], 1u) == ngroups - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (b < 256) {
-        unsigned long long s = 0;
-        for (unsigned q = 0; q < ngroups; ++q)
-            s += __hip_atomic_load(&sc.group_rows[(size_t)q * 256 + b], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        sc.out[b] = s;
-    }
+    unsigned long long t = 0;
+#pragma unroll
+    for (int u = 0; u < kHistSumBatch; ++u) t += v[u];
+    atomicAdd(&out[bin], t);
 }
 
 // ---------------------------------------------------------------------------
@@ -435,18 +447,15 @@ hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hip
 }
 
 hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream_t s) {
-    hipLaunchKernelGGL(hist_tables_kernel, dim3(1), dim3(64), 0, s, d_hist, (double *)p.htab);
+    hipLaunchKernelGGL(hist_tables_kernel, dim3(1), dim3(256), 0, s, d_hist, (double *)p.htab);
     return hipGetLastError();
 }
 
-// Scratch layout: partial rows, group rows, tickets (padded to 64 words),
-// then the 256 uint64 counts.
+// Scratch layout: the partial rows, then the 256 uint64 counts.
 static HistScratch hist_scratch(void *scratch) {
     HistScratch sc;
     sc.rows = (uint32_t *)scratch;
-    sc.group_rows = sc.rows + (size_t)kHistBlocks * 256;
-    sc.tickets = sc.group_rows + (size_t)kHistGroups * 256;
-    sc.out = (unsigned long long *)(sc.tickets + 64);
+    sc.out = (unsigned long long *)((unsigned char *)scratch + histogram_out_offset());
     return sc;
 }
 
@@ -462,12 +471,14 @@ static int histogram_blocks(uint64_t n) {
 
 static hipError_t launch_histogram_sc(const uint8_t *img, uint64_t n, const HistScratch &sc,
                                       hipStream_t s) {
-    // the tickets start at zero (a fill kernel, not a memset node)
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, sc.tickets, kHistGroups + 1);
+    const int nb = histogram_blocks(n);
+    hipLaunchKernelGGL(hist_count_kernel, dim3((unsigned)nb), dim3(kHistThreads), 0, s, img, n,
+                       sc.rows, sc.out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)histogram_blocks(n)), dim3(kHistThreads), 0,
-                       s, img, n, sc);
+    const int groups = (nb + kHistSumBatch - 1) / kHistSumBatch;
+    hipLaunchKernelGGL(hist_sum_kernel, dim3((unsigned)groups), dim3(256), 0, s,
+                       (const uint32_t *)sc.rows, nb, sc.out);
     return hipGetLastError();
 }
 
