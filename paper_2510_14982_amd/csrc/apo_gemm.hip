@@ -26,16 +26,20 @@ constexpr int kGBT = 256 / kGN;          // loader threads per row of M
 constexpr int kGQB = kGRowB / kGBT / 16; // 16-byte vectors of M per loader thread
 constexpr size_t kGemmLds = (size_t)(kGM + kGN) * kGLds;   // dynamic LDS of the product
 
-// BF16 product: 256 x 128 output tile per workgroup (4 wavefronts of 64 rows),
-// A straight from global memory into fragments, M's 128 rows through LDS in
-// chunks of kBK K, two buffers.  Both BF16 operands are stored in MFMA
+// BF16 product: 256 x 128 output tile per workgroup (8 wavefronts of 32 rows,
+// two per SIMD), A straight from global memory into fragments, M's 128 rows
+// through LDS in chunks of kBK K, two buffers.  Both BF16 operands are stored in MFMA
 // fragment order: per 16-row group and 32-K chunk one 1 KiB block, lane l's
 // 16 bytes holding row l % 16, K 8 (l / 16) .. + 7 of the chunk.
 constexpr int kBM = 256, kBN = 128, kBK = 32;
 constexpr int kBKS = kBK / 32;           // MFMA k-steps per chunk
 static_assert(kBK == 32, "one fragment block of M per chunk");
-constexpr int kBQ = 2;                   // 16-byte units each thread stages per chunk
 constexpr int kBBlk = 1024;              // bytes of one fragment block
+constexpr int kBThreads = 512;           // 8 wavefronts
+constexpr int kBRT = kBM / 16 / (kBThreads / 64);   // row tiles of 16 per wavefront
+constexpr int kBQ = (kBN / 16) * kBBlk / (16 * kBThreads);   // 16-byte units each thread
+                                                             // stages per chunk
+static_assert(kBRT == 2 && kBQ == 1, "one column group of M per wavefront and chunk");
 constexpr size_t kBBuf = (size_t)(kBN / 16) * kBBlk;   // M of one chunk: 8 blocks
 constexpr size_t kBLdsBytes = 2 * kBBuf;
 // LDS reserved at launch: more than half of a CU's 160 KB, so that a CU
@@ -277,26 +281,27 @@ __global__ __launch_bounds__(256) void gemm_obj_f32(GemmRun g) {
 // BF16 estimate product Z = bf16(y - o) bf16(M)^T with binary32 accumulation
 // on the 16 x 16 x 32 BF16 matrix cores, the same epilogue partials as the
 // binary32 product.  Workgroup tile 256 rows x 128 columns: wavefront w owns
-// rows 64 w .. 64 w + 63 (4 x 8 MFMA tiles, 128 accumulators per lane) and
-// reads its A rows from global memory straight into fragment registers, one
-// chunk ahead; the 128 rows of M the four wavefronts share are staged
-// through LDS in chunks of 128 K (two buffers, one barrier per chunk).  The
+// rows 32 w .. 32 w + 31 (2 x 8 MFMA tiles, 64 accumulators per lane; two
+// wavefronts per SIMD, so one's loads overlap the other's matrix work) and
+// reads its A rows from global memory straight into fragment registers,
+// kBDA chunks ahead; the 128 rows of M the eight wavefronts share are staged
+// through LDS in chunks of 32 K (two buffers, one barrier per chunk).  The
 // tiles of a row block are placed on one XCD (workgroup b runs on XCD b mod
 // 8), so the block's A rows are fetched from HBM once into that XCD's L2.
 // ---------------------------------------------------------------------------
 struct BChunkA {
-    u32x4 v[4][kBKS];   // [row tile][k-step]: 8 BF16 of K per lane and step
+    u32x4 v[kBRT][kBKS];   // [row tile][k-step]: 8 BF16 of K per lane and step
 };
 
 // A of chunk kc (K elements) for the lane's four row tiles: A is stored in
 // fragment order (each 16-row x 32-K block is the 64 lanes' 16 bytes in lane
 // order), so a wavefront's load of one tile is 1 KiB contiguous; aoff[i] is
 // the lane's byte offset in its row group's first block.
-__device__ __forceinline__ void bf16_load_a(const unsigned char *abase, const uint32_t (&aoff)[4],
+__device__ __forceinline__ void bf16_load_a(const unsigned char *abase, const uint32_t (&aoff)[kBRT],
                                             int kc, BChunkA &a) {
     const unsigned char *b = abase + (size_t)kc * 32;   // 1 KiB per 32 K
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kBRT; ++i)
 #pragma unroll
         for (int s = 0; s < kBKS; ++s) a.v[i][s] = *(const u32x4 *)(b + aoff[i] + 1024 * s);
 }
@@ -313,11 +318,11 @@ constexpr int kBDA = 3, kBDB = 2;
 // (c + 1) & 1.  Chunks past the end re-read the last one (unused).
 template <int PH>
 __device__ __forceinline__ void bf16_chunk(int c, int nc, const unsigned char *abase,
-                                           const uint32_t (&aoff)[4],
+                                           const uint32_t (&aoff)[kBRT],
                                            const unsigned char *bsrc, size_t bstride,
                                            unsigned char *bdst, const unsigned char *bfr,
                                            BChunkA (&a)[4], u32x4 (&bs)[2][kBQ],
-                                           f32x4 (&acc)[4][8]) {
+                                           f32x4 (&acc)[kBRT][8]) {
     {
         const size_t ob = (size_t)min(c + kBDB, nc - 1) * kBBlk;
 #pragma unroll
@@ -337,7 +342,7 @@ __device__ __forceinline__ void bf16_chunk(int c, int nc, const unsigned char *a
 #pragma unroll
         for (int j = 0; j < 8; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < kBRT; ++i)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     __builtin_bit_cast(bf16x8, cur.v[i][s]), __builtin_bit_cast(bf16x8, bv[j]),
                     acc[i][j], 0, 0, 0);
@@ -345,12 +350,13 @@ __device__ __forceinline__ void bf16_chunk(int c, int nc, const unsigned char *a
     __builtin_amdgcn_sched_barrier(0);
     unsigned char *d = bdst + ((PH + 1) & 1) * kBBuf;
 #pragma unroll
-    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(d + q * (4 * kBBlk)) = bs[(PH + 1) % 2][q];
+    for (int q = 0; q < kBQ; ++q)
+        *(u32x4 *)(d + q * ((kBThreads / 64) * kBBlk)) = bs[(PH + 1) % 2][q];
     __syncthreads();
 }
 
 template <int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gemm_obj_bf16(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_obj_bf16(
     GemmRun g) {
     extern __shared__ __align__(16) unsigned char gsm[];
     const int nrows = g.rows;   // ranks (the BF16 product has no list form)
@@ -373,25 +379,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // rows past the end are zero and their sums are not stored).  The 32-bit
     // byte offsets hold: at most 65536 rows of 1024 BF16 values (128 MiB).
     const unsigned char *abase = (const unsigned char *)g.Ab;
-    uint32_t aoff[4];
+    uint32_t aoff[kBRT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t rg = (uint32_t)(m0 + 64 * wave + 16 * i) >> 4;
+    for (int i = 0; i < kBRT; ++i) {
+        const uint32_t rg = (uint32_t)(m0 + 16 * kBRT * wave + 16 * i) >> 4;
         aoff[i] = (rg * (uint32_t)(g.Kp / 32) * 64u + (uint32_t)l) * 16u;
     }
-    // M staging: thread tid moves lane tid % 64 of column groups n0 / 16 +
-    // tid / 64 + 4 q (fragment blocks, contiguous per wavefront), to the same
-    // place of the chunk's LDS buffer
-    const size_t bstride = (size_t)4 * (g.Kp / 32) * kBBlk;   // four column groups on
+    // M staging: thread tid moves lane tid % 64 of column group n0 / 16 +
+    // tid / 64 (one fragment block per wavefront, contiguous), to the same
+    // place of the chunk's LDS buffer (kBQ == 1: one 16-byte unit a thread)
+    const size_t bstride = (size_t)(kBThreads / 64) * (g.Kp / 32) * kBBlk;   // next groups
     const unsigned char *bsrc = (const unsigned char *)g.B +
                                 ((size_t)(n0 / 16 + (tid >> 6)) * (g.Kp / 32) * kBBlk) +
                                 (size_t)(tid & 63) * 16;
     unsigned char *bdst = gsm + (tid >> 6) * kBBlk + (tid & 63) * 16;
     // fragment reads: lane l's 16 bytes of column group j's block
     const unsigned char *bfr = gsm + l * 16;
-    f32x4 acc[4][8];
+    f32x4 acc[kBRT][8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kBRT; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nc = g.Kp / kBK;   // a multiple of 4: Kp is a multiple of 128
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
     for (int c = 0; c < kBDA; ++c) bf16_load_a(abase, aoff, c * kBK, a[c]);
 #pragma unroll
-    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(bdst + q * (4 * kBBlk)) = bs[0][q];
+    for (int q = 0; q < kBQ; ++q) *(u32x4 *)(bdst + q * ((kBThreads / 64) * kBBlk)) = bs[0][q];
     __syncthreads();
     for (int c = 0; c < nc; c += 4) {
         bf16_chunk<0>(c, nc, abase, aoff, bsrc, bstride, bdst, bfr, a, bs, acc);
@@ -419,10 +425,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // columns 0..63 and 64..127 of the tile give two half partials
     const int NH = g.Np / 64;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kBRT; ++i) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int srow = m0 + 64 * wave + 16 * i + 4 * (l >> 4) + v;
+            const int srow = m0 + 16 * kBRT * wave + 16 * i + 4 * (l >> 4) + v;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 float g1 = 0.f, g2 = 0.f;
@@ -661,7 +667,7 @@ static hipError_t launch_gemm_t(const Params &p, const GemmRun &g, bool bf16, hi
                                                   (int)kBLdsLaunch);
         if (ea != hipSuccess) return ea;
         const int nM = (g.rows + kBM - 1) / kBM, nN = g.Np / kBN;
-        launch_k(p, gemm_obj_bf16<KIND>, dim3((unsigned)(nM * nN)), dim3(256), kBLdsLaunch, s, g);
+        launch_k(p, gemm_obj_bf16<KIND>, dim3((unsigned)(nM * nN)), dim3(kBThreads), kBLdsLaunch, s, g);
         return hipGetLastError();
     }
     const hipError_t ea = hipFuncSetAttribute((const void *)gemm_obj_f32<KIND>,
