@@ -95,9 +95,10 @@ __global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init)
         plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
         uniform_draws<G>(d);
         plan_decide<T, NPMAX>(p, item, it, d, c);
-        plan_pairs<T, NPMAX>(p, item, t, d, c);
-        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, false, rw);
+        plan_pick<T, NPMAX>(d, c);
+        load_rows<T, NPMAX, NCH, G>(p, c, lane, Xc, rw);
         plan_mask<T, NPMAX, G>(p, c, mwords[threadIdx.x / G], lane);
+        plan_pairs<T, NPMAX>(p, item, t, d, c);
     }
     const T *o = (const T *)p.shift;
     float *yrow = w.Yr + (size_t)item * Dp;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void gemm_cand(Params p, GemmBufs w, int init)
         if (d0 < D) {
             T y[4], ov[4];
             candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, rw.x[ch], rw.xj[ch], rw.am[ch],
-                                 rw.ap[ch], rw.am[ch], rw.ap[ch], y);
+                                 rw.ap[ch], y);
             load4(o + d0, ov);
             store4(yrow + d0, y);
             uint32_t hb[4];

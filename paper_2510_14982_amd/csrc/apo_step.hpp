@@ -157,7 +157,8 @@ __device__ __forceinline__ T weight(T fa, T fb) {
 // The protozoan's draws and every load that depends only on them, issued
 // before the decisions so they overlap the decision arithmetic: its id and
 // old fitness, and the ids / fitness of the first neighbour pair under both
-// foraging modes (k-, k+ and j of Eq. (6); i-1, i+1 of Eq. (8)).
+// foraging modes (k-, k+ and j of Eq. (6); i-1, i+1 of Eq. (8)); only the
+// decided mode's rows are loaded afterwards.
 template <typename T>
 struct Draws {
     Words s0, k1, k2, q3;
@@ -262,6 +263,17 @@ __device__ __forceinline__ void plan_decide(const Params &p, int r, const Iter &
     c.op = it.p_ah > u_op ? OP_AUTOTROPH : OP_HETEROTROPH;   // Eq. (12)
 }
 
+// The decided operation's first neighbour ids (no memory reads): X_j and the
+// first pair of Eq. (6) for an autotroph, of Eq. (8) for a heterotroph.
+template <typename T, int NPMAX>
+__device__ __forceinline__ void plan_pick(const Draws<T> &d, Plan<T, NPMAX> &c) {
+    if (c.op < OP_AUTOTROPH) return;
+    const bool autotroph = c.op == OP_AUTOTROPH;
+    c.idj = d.idj;
+    c.idm[0] = autotroph ? d.ida[0] : d.ida[1];
+    c.idp[0] = autotroph ? d.idb[0] : d.idb[1];
+}
+
 // Neighbour ids and weights of a foraging protozoan: X_j and the pairs of
 // Eq. (6) (autotroph) or Eq. (8) (heterotroph), weights of Eqs. (7), (10).
 template <typename T, int NPMAX>
@@ -309,15 +321,14 @@ __device__ __forceinline__ void plan_mask(const Params &p, Plan<T, NPMAX> &c, ui
 }
 
 // Rows a lane reads for its NCH chunks of 4 coordinates, loaded before the
-// mask is built: its own row and the neighbours of the first pair (with X_j
-// for an autotroph).
+// mask is built: its own row and the decided operation's first pair (with
+// X_j for an autotroph).
 template <typename T, int NCH>
 struct Rows {
     typedef typename V4<T>::type v4;
     v4 x[NCH];            // own row
     v4 xj[NCH];           // X_j of Eq. (6)
-    v4 am[NCH], ap[NCH];  // first pair of Eq. (6): k-, k+
-    v4 hm[NCH], hp[NCH];  // first pair of Eq. (8): i-1, i+1
+    v4 am[NCH], ap[NCH];  // first pair: k-, k+ of Eq. (6) or i-1, i+1 of Eq. (8)
 };
 
 template <typename T>
@@ -325,48 +336,37 @@ __device__ __forceinline__ typename V4<T>::type load4v(const T *p) {
     return *reinterpret_cast<const typename V4<T>::type *>(p);
 }
 
-// Own row only (c.id known), or the neighbour rows.  With `both` the first
-// pairs of both foraging modes and X_j are requested before the operation
-// is decided (from the draws alone); otherwise only the decided ones.
+// The own row (c.id known) and the decided operation's neighbour rows
+// (c.idj, c.idm[0], c.idp[0] picked); a dormant or reproducing protozoan
+// reads none.  Lanes past D read nothing.
 template <typename T, int NPMAX, int NCH, int G>
-__device__ __forceinline__ void load_rows(const Params &p, const Plan<T, NPMAX> &c,
-                                          const Draws<T> &d, int lane, const T *Xc, bool own,
-                                          bool neighbours, bool both, Rows<T, NCH> &rw) {
+__device__ __forceinline__ void load_rows(const Params &p, const Plan<T, NPMAX> &c, int lane,
+                                          const T *Xc, Rows<T, NCH> &rw) {
     const int D = p.dim, Dp = p.Dp;
     const typename V4<T>::type zero = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
         const int d0 = 4 * (lane + ch * G);
         const bool in = d0 < D;
-        if (own) rw.x[ch] = in ? load4v(Xc + (size_t)c.id * Dp + d0) : zero;
-        if (neighbours && both) {
-            rw.xj[ch] = in ? load4v(Xc + (size_t)d.idj * Dp + d0) : zero;
-            rw.am[ch] = in ? load4v(Xc + (size_t)d.ida[0] * Dp + d0) : zero;
-            rw.ap[ch] = in ? load4v(Xc + (size_t)d.idb[0] * Dp + d0) : zero;
-            rw.hm[ch] = in ? load4v(Xc + (size_t)d.ida[1] * Dp + d0) : zero;
-            rw.hp[ch] = in ? load4v(Xc + (size_t)d.idb[1] * Dp + d0) : zero;
-        } else if (neighbours) {   // the decided pair goes to am / ap
-            const bool fo = in && c.op >= OP_AUTOTROPH;
-            rw.xj[ch] = (fo && c.op == OP_AUTOTROPH) ? load4v(Xc + (size_t)c.idj * Dp + d0) : zero;
-            rw.am[ch] = fo ? load4v(Xc + (size_t)c.idm[0] * Dp + d0) : zero;
-            rw.ap[ch] = fo ? load4v(Xc + (size_t)c.idp[0] * Dp + d0) : zero;
-        }
+        rw.x[ch] = in ? load4v(Xc + (size_t)c.id * Dp + d0) : zero;
+        const bool fo = in && c.op >= OP_AUTOTROPH;
+        rw.xj[ch] = (fo && c.op == OP_AUTOTROPH) ? load4v(Xc + (size_t)c.idj * Dp + d0) : zero;
+        rw.am[ch] = fo ? load4v(Xc + (size_t)c.idm[0] * Dp + d0) : zero;
+        rw.ap[ch] = fo ? load4v(Xc + (size_t)c.idp[0] * Dp + d0) : zero;
     }
 }
 
 // Candidate values of the four coordinates d0..d0+3 of one protozoan,
 // clamped to the bounds, from the preloaded rows x (own), xj, xm, xp (first
-// pair); further pairs are read here.  Coordinates at or beyond D are set
+// pair of the decided operation); further pairs are read here.  Coordinates at or beyond D are set
 // to zero (the row padding), in x as well.
 template <typename T, int NPMAX>
 __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX> &c, int t,
                                            bool init, int d0, const T *Xc,
                                            typename V4<T>::type &x,
                                            const typename V4<T>::type &xj,
-                                           const typename V4<T>::type &am,
-                                           const typename V4<T>::type &ap,
-                                           const typename V4<T>::type &hm,
-                                           const typename V4<T>::type &hp, T y[4]) {
+                                           const typename V4<T>::type &xm,
+                                           const typename V4<T>::type &xp, T y[4]) {
     const int D = p.dim, Dp = p.Dp;
     T lb[4], ub[4];
     load4((const T *)p.lb + d0, lb);
@@ -396,12 +396,8 @@ __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX>
         }
     } else {
         T acc[4];
-        const bool au = c.op == OP_AUTOTROPH;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const T xm = au ? am[e] : hm[e], xp = au ? ap[e] : hp[e];
-            acc[e] = T(0) + c.w[0] * (xm - xp);
-        }
+        for (int e = 0; e < 4; ++e) acc[e] = T(0) + c.w[0] * (xm[e] - xp[e]);
 #pragma unroll
         for (int k = 1; k < NPMAX; ++k) {
             if (k < p.np) {
@@ -471,9 +467,10 @@ __device__ __forceinline__ void step_elem_body(const Params &p, int init, int bl
         plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
         uniform_draws<G>(d);
         plan_decide<T, NPMAX>(p, item, it, d, c);   // while the ids load
-        plan_pairs<T, NPMAX>(p, item, t, d, c);
-        load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, false, rw);
+        plan_pick<T, NPMAX>(d, c);
+        load_rows<T, NPMAX, NCH, G>(p, c, lane, Xc, rw);
         plan_mask<T, NPMAX, G>(p, c, mwords[threadIdx.x / G], lane);   // while the rows load
+        plan_pairs<T, NPMAX>(p, item, t, d, c);
     }
     (void)Fc;
 
@@ -486,7 +483,7 @@ __device__ __forceinline__ void step_elem_body(const Params &p, int init, int bl
         const int d0 = 4 * (lane + ch * G);
         if (d0 < D) {
             candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, rw.x[ch], rw.xj[ch], rw.am[ch],
-                                 rw.ap[ch], rw.am[ch], rw.ap[ch], ys[ch]);
+                                 rw.ap[ch], ys[ch]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) xs[ch][e] = rw.x[ch][e];
             if (separable) {   // objective terms of this chunk right away
@@ -729,7 +726,8 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
                 Draws<T> d;
                 plan_draws<T, NPMAX>(p, item, t, (threadIdx.x & 63) & ~(G - 1), lane, c, d);
                 plan_decide<T, NPMAX>(p, item, it, d, c);   // while the ids load
-                load_rows<T, NPMAX, NCH, G>(p, c, d, lane, Xc, true, true, true, rw);
+                plan_pick<T, NPMAX>(d, c);
+                load_rows<T, NPMAX, NCH, G>(p, c, lane, Xc, rw);
                 plan_mask<T, NPMAX, G>(p, c, s_mwords[grp], lane);   // while the rows load
                 plan_pairs<T, NPMAX>(p, item, t, d, c);
             }
@@ -739,7 +737,7 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
                 if (d0 < D) {
                     T y[4];
                     candidate4<T, NPMAX>(p, c, t, init != 0, d0, Xc, rw.x[ch], rw.xj[ch],
-                                         rw.am[ch], rw.ap[ch], rw.hm[ch], rw.hp[ch], y);
+                                         rw.am[ch], rw.ap[ch], y);
                     T ov[4], a[4], xo[4];
                     load4(o + d0, ov);
 #pragma unroll
