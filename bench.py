@@ -461,7 +461,9 @@ def main():
                     choices=["c2", "c1", "c3", "elem-large", "otsu", "c4", "np-ablation", "c5"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--kernel-iters", type=int, default=None,
+                    help="iterations of the event-timed kernel run (default: the whole run, "
+                         "so the operation mix matches the timed region's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--peaks", action="store_true",
@@ -519,7 +521,8 @@ def main():
                               "note": "whole call: kernels, copy of the counts to the host, "
                                       "stream synchronisation"}
     dt, best_f = timed_run(torch, apo, w, precision, steps, args.warmup)
-    kn, kt = kernel_times(apo, w, precision, args.kernel_iters)
+    kn, kt = kernel_times(apo, w, precision,
+                          w.max_iter if args.kernel_iters is None else args.kernel_iters)
     if not args.no_repeats:
         reps = repeat_runs(torch, apo, w, precision)
         extra["runs_evals_per_s"] = {"runs": reps, "median": sorted(reps)[len(reps) // 2],
