@@ -389,7 +389,7 @@ def np_ablation(torch, apo, args):
 
 
 def precision_run(torch, apo, args):
-    """ps 8192, D 1000, shifted-rotated Ackley, 2000 iterations: the BF16
+    """ps 8192, D 1000, shifted-rotated Ackley (or --objective), 2000 iterations: the BF16
     form (estimate + binary32 re-score of every unsettled candidate and
     acceptance; it stores what the binary32 form stores) against the
     binary32 GEMM form, with the elite re-scored in binary64 and compared
@@ -398,8 +398,8 @@ def precision_run(torch, apo, args):
     import oracle as O
     T = 2000
     w = gen.rotated_rastrigin_large(seed=args.seed, pop=8192, dim=1000, max_iter=T)
-    w.kind = "ackley"
-    w.name = "rotated_ackley_ps8192_d1000"
+    w.kind = args.objective
+    w.name = f"rotated_{args.objective}_ps8192_d1000"
     steps = T - 16 if args.steps is None else max(1, min(args.steps, T - 16))
     flops = 2.0 * w.pop * w.dim * w.dim
     forms = {}
@@ -415,7 +415,7 @@ def precision_run(torch, apo, args):
             resc, est = g.precision_stats()
         with make_handle(apo, w, prec) as h:
             _, st = h.time_gemm_stages(20)
-        p = O.Problem(dim=w.dim, pop=w.pop, lb=w.lb, ub=w.ub, kind="ackley", shift=w.shift,
+        p = O.Problem(dim=w.dim, pop=w.pop, lb=w.lb, ub=w.ub, kind=w.kind, shift=w.shift,
                       rot=w.rot)
         fo = p.objective(x)
         forms[prec] = {"evals_per_s": w.pop * steps / dt, "ms_per_step": 1000.0 * dt / steps,
@@ -431,15 +431,15 @@ def precision_run(torch, apo, args):
         "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": w.name, "pop": w.pop, "dim": w.dim, "iterations": T,
-                   "objective": "ackley", "rotated": True, "parallelism": "single GPU"},
+                   "objective": w.kind, "rotated": True, "parallelism": "single GPU"},
         "bf16_over_fp32": b["evals_per_s"] / fp["evals_per_s"],
         "equal_final_fitness": b["final_best_f_fp64"] == fp["final_best_f_fp64"],
         "forms": forms,
         "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA_TFLOPS,
-                     "traffic": measured_traffic("c5"),
-                     "kernel": "gemm_obj_bf16<ACKLEY> (BF16 estimate of z = M (y - o) with "
-                               "fused objective sums)",
+                     "traffic": measured_traffic("c5") if w.kind == "ackley" else None,
+                     "kernel": f"gemm_obj_bf16<{w.kind.upper()}> (BF16 estimate of "
+                               "z = M (y - o) with fused objective sums)",
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": (w.pop + 1024) * 1024 * 2},
     }
@@ -459,6 +459,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="c2",
                     choices=["c2", "c1", "c3", "elem-large", "otsu", "c4", "np-ablation", "c5"])
+    ap.add_argument("--objective", default="ackley", choices=["ackley", "rastrigin", "sphere"],
+                    help="objective of the precision workload (c5); its configuration is Ackley")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=None,

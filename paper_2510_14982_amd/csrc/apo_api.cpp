@@ -672,21 +672,52 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         std::memcpy(gmd.data(), M, (size_t)dim * dim * 8);
         if (opt->objective.shift) std::memcpy(go.data(), opt->objective.shift, (size_t)dim * 8);
         if (p.gb.bf16) {
-            // BF16 M in MFMA fragment order: per 16-row group n / 16 and 32-K
-            // chunk k / 32 a block of 64 lanes x 8 values, lane n % 16 +
-            // 16 ((k % 32) / 8) holding k % 8 = 0..7
+            // BF16 M (round to nearest even; M in binary32) in MFMA fragment
+            // order: per 16-row group n / 16 and 32-K chunk k / 32 a block of
+            // 64 lanes x 8 values, lane n % 16 + 16 ((k % 32) / 8) holding
+            // k % 8 = 0..7
             gmb.assign((size_t)L.Np * L.Kp * 2, 0);
             uint16_t *mb = reinterpret_cast<uint16_t *>(gmb.data());
             const size_t kch = (size_t)L.Kp / 32;
+            auto bf16_bits = [](float x) {   // finite x: round to nearest even
+                uint32_t u;
+                std::memcpy(&u, &x, 4);
+                u += 0x7FFFu + ((u >> 16) & 1u);
+                return (uint16_t)(u >> 16);
+            };
+            auto bf16_value = [](uint16_t h) {
+                const uint32_t u = (uint32_t)h << 16;
+                float f;
+                std::memcpy(&f, &u, 4);
+                return f;
+            };
+            // row and column sums of |bf16(M) - M| and |M| (binary64: each sum
+            // of at most 1024 terms is exact to ~1e-13 relative; the bounds below
+            // are rounded up with margin)
+            std::vector<double> rd(dim, 0.0), cd(dim, 0.0), ra(dim, 0.0), ca(dim, 0.0);
             for (size_t n = 0; n < (size_t)L.Np; ++n)
                 for (size_t k = 0; k < (size_t)L.Kp; ++k) {
-                    uint32_t u;
-                    std::memcpy(&u, &mf[n * L.Kp + k], 4);
-                    u += 0x7FFFu + ((u >> 16) & 1u);   // finite entries of an orthogonal M
+                    const float m = mf[n * L.Kp + k];
+                    const uint16_t hi = bf16_bits(m);
                     const size_t lane = (n & 15) + 16 * ((k & 31) >> 3);
-                    mb[(((n >> 4) * kch + (k >> 5)) * 64 + lane) * 8 + (k & 7)] =
-                        (uint16_t)(u >> 16);
+                    mb[(((n >> 4) * kch + (k >> 5)) * 64 + lane) * 8 + (k & 7)] = hi;
+                    if (n < (size_t)dim && k < (size_t)dim) {
+                        const double dm = std::fabs((double)m - (double)bf16_value(hi));
+                        const double am = std::fabs((double)m);
+                        rd[n] += dm;
+                        cd[k] += dm;
+                        ra[n] += am;
+                        ca[k] += am;
+                    }
                 }
+            auto holder = [](const std::vector<double> &r, const std::vector<double> &c) {
+                double mr = 0.0, mc = 0.0;
+                for (double v : r) mr = v > mr ? v : mr;
+                for (double v : c) mc = v > mc ? v : mc;
+                return std::sqrt(mr * mc) * (1.0 + 1e-9);
+            };
+            p.gb.nrm_dM = std::nextafter((float)holder(rd, cd), INFINITY);
+            p.gb.nrm_absM = std::nextafter((float)holder(ra, ca), INFINITY);
         }
     }
     if (p.rotated && !gf) {

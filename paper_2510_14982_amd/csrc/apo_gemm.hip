@@ -535,21 +535,38 @@ __global__ __launch_bounds__(256) void gemm_classify(Params p, GemmRun g, GemmBu
         row_sums(g, r, s1, s2);
         fhat = row_objective(p.kind, D, s1, s2);
         const float fold = ((const float *)p.Fs)[r];
-        // Coordinate error: BF16 operands (unit roundoff 2^-8 each) and two
-        // binary32 accumulations over D terms, times sum_j |M_ij| |a_j| <=
-        // ||a||_2 (orthogonal rows; the BF16 rows' norms stay within 1.01).
-        const float e = (1.01f * 0.0078125f + 2.f * (float)(D + 2) * 5.9604645e-8f) * 1.01f *
-                        w.anorm[r];
-        const float ce = fminf(2.f, 6.2831853f * e);        // |cos 2 pi a - cos 2 pi b|
-        const float gD = 2.f * (float)D * 5.9604645e-8f;     // binary32 evaluation of sums
+        // Error of the estimate's coordinate vector against the binary32
+        // form's, in the 2-norm (a = y - o in binary32, z = M a, M in binary32,
+        // the estimate's operands a_b = bf16(a) and M_b = bf16(M)):
+        //   operand rounding  M_b a_b - M a = M (a_b - a) + (M_b - M) a_b, with
+        //     ||M||_2 <= 1.01 (orthogonal rows in binary32),
+        //     ||a_b - a||_2 <= 2^-8 ||a||_2 and ||M_b - M||_2 <= nrm_dM;
+        //   accumulation      the binary32 form's sums over D rounded products
+        //     and the estimate's over D exact ones: |error_i| <= gam
+        //     sum_j |M_ij| |a_j| with gam = gamma_(D+2) (times (1 + 2^-8)^2 for
+        //     the rounded BF16 operands), whose 2-norm is <= gam || |M| ||_2
+        //     ||a||_2, || |M| ||_2 <= nrm_absM.
+        const float ub = 0.00390625f;                                  // 2^-8
+        const float u32 = 5.9604645e-8f;                               // 2^-24
+        const float gam = (float)(D + 2) * u32 / (1.f - (float)(D + 2) * u32);
+        const float an = 1.001f * w.anorm[r];   // ||a||_2 as summed in binary32
+        const float E = (1.01f * ub + w.nrm_dM * (1.f + ub) +
+                         gam * (1.f + (1.f + ub) * (1.f + ub)) * w.nrm_absM) * an;
+        const float sD = sqrtf((float)D);
+        // sum_i |cos 2 pi a_i - cos 2 pi b_i| <= min(2 D, 2 pi ||a - b||_1),
+        // ||.||_1 <= sqrt(D) ||.||_2
+        const float dc = fminf(2.f * (float)D, 6.2831853f * sD * E);
+        const float gD = 2.f * (float)D * u32;               // binary32 evaluation of sums
         float B;
         if (p.kind == K_ACKLEY) {
+            // r = ||z||_2 / sqrt(D) moves by at most E / sqrt(D); 20 exp(-0.2 r) is
+            // 4-Lipschitz in r; exp(S2 / D) <= e
             const float rr = sqrtf(s1 / (float)D);
-            B = 4.f * e + 2.7182818f * ce + gD * (4.f * rr + 2.7182818f);
+            B = 4.f * E / sD + 2.7182818f * dc / (float)D + gD * (4.f * rr + 2.7182818f);
         } else {
+            // | ||z^||^2 - ||z~||^2 | <= E (2 ||z^||_2 + E)
             const float zn = sqrtf(s2);                      // ||z^||_2
-            B = 2.f * e * sqrtf((float)D) * zn + (float)D * e * e +
-                (p.kind == K_RASTRIGIN ? 10.f * (float)D * ce : 0.f) +
+            B = E * (2.f * zn + E) + (p.kind == K_RASTRIGIN ? 10.f * dc : 0.f) +
                 gD * (s2 + (p.kind == K_RASTRIGIN ? 20.f * (float)D : 0.f));
         }
         B = B * 1.05f + 1e-6f * (fabsf(fhat) + fabsf(fold));

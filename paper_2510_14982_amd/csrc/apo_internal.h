@@ -48,6 +48,9 @@ struct GemmBufs {
     double *z64;          // [dim] z of the elite re-score
     int32_t Kp, Np;       // K and N padded to 128
     int32_t bf16;         // 1: BF16 estimate + binary32 re-score
+    float nrm_dM;         // upper bound of ||bf16(M) - M||_2 (M in binary32), from its row
+                          // and column sums (||A||_2 <= sqrt(||A||_1 ||A||_inf))
+    float nrm_absM;       // upper bound of || |M| ||_2, the same way
 };
 
 // Everything a kernel needs, passed by value.  Element pointers are typed
