@@ -134,11 +134,16 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
  * lower.  Asynchronous.  APO_E_DONE once t == max_iter. */
 int apo_step(apo_t *h);
 
-/* Up to iters more iterations (clipped to max_iter - t).  Returns the number
- * executed (>= 0) or a status.  The sort and step kernels of each iteration
- * are replayed from HIP graphs, captured on the first call (apo_run(h, 0)
- * captures them and executes nothing, so a later timed call does not
- * include the capture). */
+/* Up to iters more iterations (clipped to max_iter - t): Algorithm 1's loop
+ * body, as apo_step, repeated.  Returns the number executed (>= 0) or a
+ * status.  The sort and step kernels of each iteration are replayed from HIP
+ * graphs, captured on the first call (apo_run(h, 0) captures them and
+ * executes nothing, so a later timed call does not include the capture).
+ * A run whose whole population fits one workgroup of the step (elementwise
+ * objectives with pop x lanes <= 256, pop <= 256; e.g. pop 32 at dim 10)
+ * instead runs all its iterations in one single-workgroup launch (the
+ * persistent form: sort and step separated by workgroup barriers); the
+ * results are the same bit for bit. */
 int apo_run(apo_t *h, int32_t iters);
 
 /* The best protozoan (lowest fitness; NaN never wins; lowest id on ties):

@@ -838,6 +838,13 @@ int apo_run(apo_t *h, int32_t iters) {
     if (h->poisoned) return APO_E_DEVICE;
     int32_t n = h->T - h->t;
     if (iters < n) n = iters;
+    if (apok::persist_form(h->p)) {
+        // the whole run in one workgroup: all n iterations in one launch
+        if (n <= 0) return 0;
+        APO_HIP(h, apok::launch_persist(h->p, h->fp64, h->t, n, h->stream));
+        h->t += n;
+        return n;
+    }
     if (!h->graph_tried) {   // apo_run(h, 0) only does this
         h->graph_tried = true;
         capture_iterations(h, 1, &h->graph[0], &h->graph_exec[0]);

@@ -117,6 +117,9 @@ struct BatchLaunch {
 hipError_t launch_init(const Params &p, bool fp64, hipStream_t s);
 hipError_t launch_rank(const Params &p, bool fp64, hipStream_t s);
 hipError_t launch_step(const Params &p, bool fp64, hipStream_t s);
+// The persistent form: iterations t0 + 1 .. t0 + n of a run with
+// persist_form(p), sort and step of each, in one single-workgroup launch.
+hipError_t launch_persist(const Params &p, bool fp64, int t0, int n, hipStream_t s);
 hipError_t launch_best(const Params &p, bool fp64, int cur, double *out_row, hipStream_t s);
 hipError_t launch_hist_tables(const Params &p, const uint64_t *d_hist, hipStream_t s);
 // 256-bin histogram of n bytes into scratch (histogram_scratch_bytes():
@@ -191,6 +194,14 @@ inline int step_blocks(const Params &p) {
 // Dynamic LDS of a run's step launch.
 inline size_t step_lds_bytes(const Params &p, bool fp64) {
     return tile_form(p) ? tile_lds_bytes(p, fp64) : 0;
+}
+
+// Whether a run takes the persistent form of apo_run (one workgroup running
+// every iteration): the elementwise step with the whole population in one
+// workgroup of 256 threads, and a sort of one LDS workgroup.
+inline bool persist_form(const Params &p) {
+    return !p.gemm && !tile_form(p) && p.pop <= 256 &&
+           (long long)p.pop * lanes_for_dim(p.dim) <= 256;
 }
 
 // Instantiation key: precision, form, lanes, chunks, rows and whether np > 1

@@ -125,57 +125,8 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
     }
 }
 
-// LDS form (ps <= kRankLdsMax): the run's keys are staged in LDS and each
-// of the workgroup's 256 threads counts, for one protozoan, the keys that
-// precede its own (broadcast reads), so a workgroup ranks 256 protozoa.
-// Fewest workgroups: the form of small runs and of batches; a single run
-// of a few hundred or more protozoa prefers the register form's many
-// workgroups (lower latency).
-constexpr int kRankSmall = kRankLdsMax;
-
-template <typename T>
-__device__ __forceinline__ void rank_small_body(const Params &p, int blk) {
-    __shared__ uint64_t s_k[kRankSmall];
-    __shared__ uint32_t s_keys[24];
-    __shared__ int32_t s_mdr;
-    const T *F = (const T *)p.F;
-    const int ps = p.pop;
-    const int tid = threadIdx.x, wave = tid >> 6;
-    const int t = __hip_atomic_load(&p.ctrl->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-    T f[kRankSmall / 256];
-#pragma unroll
-    for (int u = 0; u < kRankSmall / 256; ++u) {
-        const int j = tid + 256 * u;
-        f[u] = F[j < ps ? j : ps - 1];
-    }
-    if (wave == 3) open_iteration(p, t, s_keys, &s_mdr);
-#pragma unroll
-    for (int u = 0; u < kRankSmall / 256; ++u) {
-        const int j = tid + 256 * u;
-        if (j < ps) s_k[j] = RankKey<T>::make(f[u], j);
-    }
-    __syncthreads();
-    const int i = blk * 256 + tid;
-    if (i < ps) {
-        const uint64_t ki = s_k[i];
-        int rank = 0;
-        for (int j = 0; j < ps; ++j) rank += RankKey<T>::before(s_k[j], j, ki, i) ? 1 : 0;
-        p.perm[rank] = i;
-        ((T *)p.Fs)[rank] = F[i];
-        Subset drs;
-        subset_shape(drs, (uint32_t)ps);
-#pragma unroll
-        for (int q = 0; q < 24; ++q) drs.k[q] = s_keys[q];
-        p.drf[rank] = subset_has(drs, (uint32_t)rank, (uint32_t)s_mdr) ? 1 : 0;
-    }
-    if (blk == 0 && tid == 64) {   // publish the iteration for the step
-        p.ctrl->m_dr = s_mdr;
-        p.ctrl->p_ah = p.p_ah[t];
-        p.ctrl->fscale = p.fscale[t];
-        p.ctrl->cnear = p.cnear[t];
-        p.ctrl->t_next = t;
-    }
-}
+// The LDS form of the sort (rank_small_body) is in apo_step.hpp: the persistent
+// form of small runs uses it too.
 
 template <typename T>
 __device__ __forceinline__ void rank_any(const Params &p, int blk) {
@@ -394,6 +345,13 @@ static hipError_t launch_step_any(const Params &p, bool fp64, int init, hipStrea
     const bool tile = p.rotated || p.kind == K_KAPUR || p.kind == K_OTSU;
     if (tile) return fp64 ? launch_tile_f64(p, init, s) : launch_tile_f32(p, init, s);
     return fp64 ? launch_elem_f64(p, init, s) : launch_elem_f32(p, init, s);
+}
+
+hipError_t launch_persist_f32(const Params &p, int t0, int n, hipStream_t s);
+hipError_t launch_persist_f64(const Params &p, int t0, int n, hipStream_t s);
+
+hipError_t launch_persist(const Params &p, bool fp64, int t0, int n, hipStream_t s) {
+    return fp64 ? launch_persist_f64(p, t0, n, s) : launch_persist_f32(p, t0, n, s);
 }
 
 hipError_t launch_init(const Params &p, bool fp64, hipStream_t s) {

@@ -128,6 +128,62 @@ __device__ __forceinline__ void open_iteration(const Params &p, int t, uint32_t 
     }
 }
 
+// LDS form (ps <= kRankLdsMax): the run's keys are staged in LDS and each
+// of the workgroup's 256 threads counts, for one protozoan, the keys that
+// precede its own (broadcast reads), so a workgroup ranks 256 protozoa.
+// Fewest workgroups: the form of small runs and of batches; a single run
+// of a few hundred or more protozoa prefers the register form's many
+// workgroups (lower latency).
+constexpr int kRankSmall = kRankLdsMax;
+
+template <typename T>
+__device__ __forceinline__ void rank_small_body(const Params &p, int blk, int t_open = 0) {
+    __shared__ uint64_t s_k[kRankSmall];
+    __shared__ uint32_t s_keys[24];
+    __shared__ int32_t s_mdr;
+    const T *F = (const T *)p.F;
+    const int ps = p.pop;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    // the iteration this sort opens: the one after the last completed, or
+    // t_open when the caller runs the iterations itself (persistent form)
+    const int t = t_open > 0 ? t_open
+                             : __hip_atomic_load(&p.ctrl->t, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT) + 1;
+    T f[kRankSmall / 256];
+#pragma unroll
+    for (int u = 0; u < kRankSmall / 256; ++u) {
+        const int j = tid + 256 * u;
+        f[u] = F[j < ps ? j : ps - 1];
+    }
+    if (wave == 3) open_iteration(p, t, s_keys, &s_mdr);
+#pragma unroll
+    for (int u = 0; u < kRankSmall / 256; ++u) {
+        const int j = tid + 256 * u;
+        if (j < ps) s_k[j] = RankKey<T>::make(f[u], j);
+    }
+    __syncthreads();
+    const int i = blk * 256 + tid;
+    if (i < ps) {
+        const uint64_t ki = s_k[i];
+        int rank = 0;
+        for (int j = 0; j < ps; ++j) rank += RankKey<T>::before(s_k[j], j, ki, i) ? 1 : 0;
+        p.perm[rank] = i;
+        ((T *)p.Fs)[rank] = F[i];
+        Subset drs;
+        subset_shape(drs, (uint32_t)ps);
+#pragma unroll
+        for (int q = 0; q < 24; ++q) drs.k[q] = s_keys[q];
+        p.drf[rank] = subset_has(drs, (uint32_t)rank, (uint32_t)s_mdr) ? 1 : 0;
+    }
+    if (blk == 0 && tid == 64) {   // publish the iteration for the step
+        p.ctrl->m_dr = s_mdr;
+        p.ctrl->p_ah = p.p_ah[t];
+        p.ctrl->fscale = p.fscale[t];
+        p.ctrl->cnear = p.cnear[t];
+        p.ctrl->t_next = t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Per-protozoan plan of one iteration: which operation, its mask, scalars
 // and neighbours.  Every lane of the protozoan's group computes the same
@@ -442,13 +498,16 @@ __device__ __forceinline__ void candidate4(const Params &p, const Plan<T, NPMAX>
 // Fused elementwise step.  G lanes per protozoan (a power of two <= 64, so a
 // group never straddles a wavefront), NCH chunks of 4 coordinates per lane.
 // ---------------------------------------------------------------------------
+// `itp`: the iteration and its scalars when the caller knows them (the
+// persistent form); nullptr reads them from the control block.
 template <typename T, int G, int NCH, int NPMAX>
-__device__ __forceinline__ void step_elem_body(const Params &p, int init, int blk) {
+__device__ __forceinline__ void step_elem_body(const Params &p, int init, int blk,
+                                               const Iter *itp = nullptr) {
     const int lane = threadIdx.x & (G - 1);
     const int item = (blk * 256 + threadIdx.x) / G;
     if (item >= p.pop) return;
     const int D = p.dim, Dp = p.Dp;
-    const Iter it = load_iter(p, init);
+    const Iter it = itp ? *itp : load_iter(p, init);
     const int t = it.t;
     const int src = (t + 1) & 1, dst = t & 1;
     const T *Xc = (const T *)p.X[src];
@@ -579,6 +638,43 @@ __global__ __launch_bounds__(256) void step_elem_batch(const Params *runs, const
                                                        int init) {
     const int2 b = blocks[blockIdx.x];
     step_elem_body<T, G, NCH, NPMAX>(runs[b.x], init, b.y);
+}
+
+// Persistent form of a run whose whole population one workgroup of the
+// elementwise step holds (ps G <= 256 lanes, ps <= 256): a single workgroup
+// runs n iterations, each the sort (LDS form, the whole population) and the
+// step, separated by workgroup barriers only -- the barriers also make each
+// phase's global writes (order, fitness by rank, Dr flags; rows and fitness)
+// visible to the next phase, all of it on one CU.  The device code is the
+// two-kernel iteration's, so the results are the same bit for bit.
+template <typename T, int G, int NCH, int NPMAX>
+__global__ __launch_bounds__(256) void run_elem_persist(Params p, int t0, int n) {
+    for (int k = 1; k <= n; ++k) {
+        const int t = t0 + k;
+        rank_small_body<T>(p, 0, t);
+        __syncthreads();
+        Iter it;
+        it.t = t;
+        it.p_ah = p.p_ah[t];
+        it.fscale = p.fscale[t];
+        it.cnear = p.cnear[t];
+        step_elem_body<T, G, NCH, NPMAX>(p, 0, 0, &it);
+        __syncthreads();
+    }
+}
+
+template <typename T, int NPMAX>
+hipError_t launch_persist_t(const Params &p, int t0, int n, hipStream_t s) {
+    const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
+    if (!persist_form(p) || n < 1) return hipErrorInvalidValue;
+#define APO_PERSIST(GG, CC)                                                                  \
+    if (G == GG && NCH == CC) {                                                              \
+        launch_k(p, run_elem_persist<T, GG, CC, NPMAX>, dim3(1), dim3(256), 0, s, p, t0, n); \
+        return hipGetLastError();                                                            \
+    }
+    APO_ELEM_SHAPES(APO_PERSIST)
+#undef APO_PERSIST
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

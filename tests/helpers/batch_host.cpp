@@ -281,6 +281,7 @@ namespace apok {
 hipError_t launch_init(const Params &, bool, hipStream_t) { return hipSuccess; }
 hipError_t launch_rank(const Params &, bool, hipStream_t) { return hipSuccess; }
 hipError_t launch_step(const Params &, bool, hipStream_t) { return hipSuccess; }
+hipError_t launch_persist(const Params &, bool, int, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_best(const Params &, bool, int, double *, hipStream_t) { return hipSuccess; }
 hipError_t launch_hist_tables(const Params &, const uint64_t *, hipStream_t) { return hipSuccess; }
 size_t histogram_scratch_bytes() { return kHistScratchBytes; }

@@ -194,6 +194,38 @@ def test_graph_replay_equals_single_steps_and_is_deterministic():
         assert a[2] == b[2] == c[2] == 40
 
 
+@pytest.mark.parametrize("kw", [
+    dict(dim=10, pop=32, kind="rastrigin", precision="fp64", max_iter=60),
+    dict(dim=16, pop=64, kind="rosenbrock", precision="fp32", max_iter=40, pf_max=0.5),
+    dict(dim=10, pop=50, kind="sphere", precision="fp64", max_iter=30, np_pairs=3),
+    dict(dim=3, pop=4, kind="ackley", precision="fp32", max_iter=25, pf_max=1.0),
+], ids=["c1_fp64", "rosenbrock_fp32_full_wg", "sphere_np3", "tiny_all_dr"])
+def test_persistent_run_equals_single_steps(kw):
+    """Runs whose whole population fits one workgroup take the persistent
+    form in apo_run (one launch for all iterations); the state after it is
+    the two-kernel iteration's bit for bit, whatever the chunking of the
+    calls, and every iteration count and the best agree."""
+    apo = need_gpu()
+    print(f"[run] persistent form vs single steps {kw}", flush=True)
+    T = kw["max_iter"]
+    g1, _ = make_pair(apo, seed=9, **kw)
+    g2, _ = make_pair(apo, seed=9, **kw)
+    g3, _ = make_pair(apo, seed=9, **kw)
+    with g1, g2, g3:
+        assert g1.run(T + 5) == T
+        for _ in range(T):
+            assert g2.step()
+        assert g3.run(7) == 7 and g3.run(1) == 1 and g3.run(T) == T - 8
+        a, b, c = g1.get_state(), g2.get_state(), g3.get_state()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+        assert a[2] == b[2] == c[2] == T
+        assert g1.run(3) == 0
+        x1, f1, e1 = g1.best()
+        x2, f2, e2 = g2.best()
+        assert np.array_equal(x1, x2) and f1 == f2 and e1 == e2 == kw["pop"] * (T + 1)
+
+
 def test_checkpoint_resume_bit_identical():
     apo = need_gpu()
     print("[run] checkpoint resume", flush=True)
