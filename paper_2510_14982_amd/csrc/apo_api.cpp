@@ -101,11 +101,17 @@ Layout make_layout(int dim, int pop, const apo_options &o) {
     return L;
 }
 
-// Rows per workgroup of a single handle's tiled step: wide tiles only when
-// the run alone still gives every CU a workgroup.
-int single_tile_rows(int dim, int pop) {
-    const int wide = apok::tile_rows_wide(apok::lanes_for_dim(dim));
-    return (wide > 16 && pop >= 256 * wide) ? wide : 16;
+// Rows per workgroup of a single handle's tiled step: wide tiles when the
+// run alone still gives every CU a workgroup, or when one wide tile holds the
+// whole run; else one MFMA row block.
+int single_tile_rows(int dim, int pop, int es) {
+    const int G = apok::lanes_for_dim(dim), wide = apok::tile_rows_wide(G);
+    if (wide > 16 && pop >= 256 * wide) return wide;
+    // one wide tile holds the whole run: the persistent form of apo_run
+    if (wide > 16 && pop <= wide && pop <= 256 &&
+        apok::tile_shape_ok(dim, G, apok::chunks_for(dim, G), wide, es))
+        return wide;
+    return 16;
 }
 
 int check_args(int32_t dim, const double *lb, const double *ub, int32_t pop, int32_t np,
@@ -146,8 +152,9 @@ int check_args(int32_t dim, const double *lb, const double *ub, int32_t pop, int
         const int lim = is_threshold(kind) ? 512 : (opt->precision == APO_FP64 ? 256 : 512);
         if (dim > lim) return APO_E_UNSUPPORTED;
         const int G = apok::lanes_for_dim(dim);
-        if (!apok::tile_shape_ok(dim, G, apok::chunks_for(dim, G), single_tile_rows(dim, pop),
-                                 opt->precision == APO_FP64 ? 8 : 4))
+        const int es = opt->precision == APO_FP64 ? 8 : 4;
+        if (!apok::tile_shape_ok(dim, G, apok::chunks_for(dim, G), single_tile_rows(dim, pop, es),
+                                 es))
             return APO_E_UNSUPPORTED;
     } else if (!apok::elem_shape_built(apok::lanes_for_dim(dim), apok::chunks_for_dim(dim))) {
         return APO_E_UNSUPPORTED;
@@ -580,7 +587,7 @@ int apo_create(int32_t dim, const double *lb, const double *ub, int32_t pop, int
     p.rotated = opt->objective.rot != nullptr;
     p.Nt = L.Nt;
     p.Ks = L.Ks;
-    p.rows = single_tile_rows(dim, pop);
+    p.rows = single_tile_rows(dim, pop, (int)h->es);
     p.rank_lds = pop <= 256 ? 1 : 0;   // one workgroup ranks the whole run
     p.gemm = gf ? 1 : 0;
     p.trace = (opt->flags & APO_FLAG_TRACE) ? 1 : 0;

@@ -197,11 +197,13 @@ inline size_t step_lds_bytes(const Params &p, bool fp64) {
 }
 
 // Whether a run takes the persistent form of apo_run (one workgroup running
-// every iteration): the elementwise step with the whole population in one
-// workgroup of 256 threads, and a sort of one LDS workgroup.
+// every iteration): the whole population in one workgroup of the step --
+// the elementwise step's 256 threads, or one tile -- and a sort of one LDS
+// workgroup.
 inline bool persist_form(const Params &p) {
-    return !p.gemm && !tile_form(p) && p.pop <= 256 &&
-           (long long)p.pop * lanes_for_dim(p.dim) <= 256;
+    if (p.gemm || p.pop > 256) return false;
+    if (tile_form(p)) return p.pop <= tile_rows(p);
+    return (long long)p.pop * lanes_for_dim(p.dim) <= 256;
 }
 
 // Instantiation key: precision, form, lanes, chunks, rows and whether np > 1

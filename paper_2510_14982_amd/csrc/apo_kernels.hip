@@ -349,8 +349,12 @@ static hipError_t launch_step_any(const Params &p, bool fp64, int init, hipStrea
 
 hipError_t launch_persist_f32(const Params &p, int t0, int n, hipStream_t s);
 hipError_t launch_persist_f64(const Params &p, int t0, int n, hipStream_t s);
+hipError_t launch_tile_persist_f32(const Params &p, int t0, int n, hipStream_t s);
+hipError_t launch_tile_persist_f64(const Params &p, int t0, int n, hipStream_t s);
 
 hipError_t launch_persist(const Params &p, bool fp64, int t0, int n, hipStream_t s) {
+    if (tile_form(p))
+        return fp64 ? launch_tile_persist_f64(p, t0, n, s) : launch_tile_persist_f32(p, t0, n, s);
     return fp64 ? launch_persist_f64(p, t0, n, s) : launch_persist_f32(p, t0, n, s);
 }
 

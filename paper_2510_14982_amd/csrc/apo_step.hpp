@@ -710,12 +710,12 @@ __device__ __forceinline__ int mfma_out_row<double>(int l, int v) { return 4 * v
 // P (probability), S (p ln p) and M1 (level x probability); empty classes
 // add nothing.  Each lane adds its classes; the team total is the same in
 // every lane.  F is minus the criterion.
-template <typename T>
+template <typename T, int TT>
 __device__ __forceinline__ double threshold_objective_team(const Params &p, const T *yrow,
                                                            int *ts, int tl, bool live) {
     const int k = p.dim;
     if (live) {
-        for (int c = tl; c < k; c += 32) {
+        for (int c = tl; c < k; c += TT) {
             const int v = (int)rint((double)yrow[c]);
             int pos = 0;
             for (int q = 0; q < k; ++q) {
@@ -732,7 +732,7 @@ __device__ __forceinline__ double threshold_objective_team(const Params &p, cons
     const double muT = M1[256];
     double part = 0.0;
     if (live) {
-        for (int c = tl; c <= k; c += 32) {
+        for (int c = tl; c <= k; c += TT) {
             const int a = c == 0 ? 0 : ts[c - 1];
             const int b = c < k ? ts[c] : 256;
             const double omega = P[b] - P[a];
@@ -746,7 +746,23 @@ __device__ __forceinline__ double threshold_objective_team(const Params &p, cons
             }
         }
     }
-    return -group_sum<32>(part);
+    return -group_sum<TT>(part);
+}
+
+// The objective of the first nrows rows of a tile by teams of TT lanes
+// (512 / TT teams, rows in turn).  With k + 1 <= TT every lane holds at most
+// one class, and the team sum equals that of a wider team bit for bit (the
+// added lanes hold exact zeros), so the team size is a choice of speed only.
+template <typename T, int TT>
+__device__ __forceinline__ void threshold_rows(const Params &p, const T *Ys, int LS, int *Zi,
+                                               int nrows, const int32_t *s_id, T *s_fnew) {
+    const int tl = threadIdx.x & (TT - 1);
+    for (int row = threadIdx.x / TT; row < nrows; row += 512 / TT) {
+        const bool live = s_id[row] >= 0;
+        const double f =
+            threshold_objective_team<T, TT>(p, Ys + row * LS, Zi + row * (p.dim + 1), tl, live);
+        if (tl == 0 && live) s_fnew[row] = T(f);
+    }
 }
 
 // LDS row stride (elements) of the tile's row buffers (tile_row_stride of
@@ -943,14 +959,20 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
 
     // phase 3: objective per protozoan
     if (thresholds) {
-        // 32-lane teams (the 512 threads are 16 teams), rows in turn
-        const int tl = threadIdx.x & 31;
-        for (int row = threadIdx.x >> 5; row < TM; row += NT / 32) {
-            const bool live = s_id[row] >= 0;
-            int *ts = (int *)Zs + row * (D + 1);
-            const double f = threshold_objective_team<T>(p, Ys + row * LS, ts, tl, live);
-            if (tl == 0 && live) s_fnew[row] = T(f);
-        }
+        // teams of the smallest power of two >= k + 1 lanes (at most 32),
+        // over the rows that hold a protozoan
+        const int nrows = p.pop - r0 < TM ? p.pop - r0 : TM;
+        int *Zi = (int *)Zs;
+        if (D + 1 <= 2)
+            threshold_rows<T, 2>(p, Ys, LS, Zi, nrows, s_id, s_fnew);
+        else if (D + 1 <= 4)
+            threshold_rows<T, 4>(p, Ys, LS, Zi, nrows, s_id, s_fnew);
+        else if (D + 1 <= 8)
+            threshold_rows<T, 8>(p, Ys, LS, Zi, nrows, s_id, s_fnew);
+        else if (D + 1 <= 16)
+            threshold_rows<T, 16>(p, Ys, LS, Zi, nrows, s_id, s_fnew);
+        else
+            threshold_rows<T, 32>(p, Ys, LS, Zi, nrows, s_id, s_fnew);
     } else if (separable) {
         // the row sums of the column-tile partials are taken in phase 4 by
         // each row's own group (the partials are visible since phase 2)
@@ -1039,6 +1061,28 @@ __global__ __launch_bounds__(512) void step_tile_batch(const Params *runs, const
     step_tile_body<T, G, NCH, NPMAX, TM>(runs[b.x], init, b.y);
 }
 
+// Persistent form of a tiled run whose population one tile holds (ps <= TM,
+// ps <= 256): as run_elem_persist, one workgroup runs n iterations of the
+// sort (LDS form; its threads past 256 take no part) and the tiled step,
+// separated by workgroup barriers; the iteration is closed in the control
+// block at the end.
+template <typename T, int G, int NCH, int NPMAX, int TM>
+__global__ __launch_bounds__(512) void run_tile_persist(Params p, int t0, int n) {
+    for (int k = 1; k <= n; ++k) {
+        const int t = t0 + k;
+        rank_small_body<T>(p, 0, t);
+        __syncthreads();
+        Iter it;
+        it.t = t;
+        it.p_ah = p.p_ah[t];
+        it.fscale = p.fscale[t];
+        it.cnear = p.cnear[t];
+        step_tile_body<T, G, NCH, NPMAX, TM>(p, 0, 0, &it);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && n > 0) p.ctrl->t = t0 + n;   // iterations closed
+}
+
 
 // A launch of one handle (b == nullptr: grid of the run's own blocks, lds
 // from its shape) or of a batch (b: the runs of one kernel shape, `p` one
@@ -1072,6 +1116,28 @@ hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLa
 #undef APO_TILE
         return hipErrorInvalidValue;
     }
+}
+
+template <typename T, int NPMAX>
+hipError_t launch_tile_persist_t(const Params &p, int t0, int n, hipStream_t s) {
+    const int G = tile_lanes(p), NCH = tile_chunks(p), TMr = tile_rows(p);
+    if (!persist_form(p) || n < 1 || NCH < 0) return hipErrorInvalidValue;
+    const size_t lds = tile_lds_bytes(p, sizeof(T) == 8);
+#define APO_TILE_PERSIST(GG, CC, TMM)                                                        \
+    if (G == GG && NCH == CC && TMr == TMM) {                                                \
+        const void *fn = (const void *)run_tile_persist<T, GG, CC, NPMAX, TMM>;              \
+        if (lds > 65536) {                                                                   \
+            const hipError_t ea =                                                            \
+                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+            if (ea != hipSuccess) return ea;                                                 \
+        }                                                                                    \
+        launch_k(p, run_tile_persist<T, GG, CC, NPMAX, TMM>, dim3(1), dim3(512), lds, s, p, t0, \
+                 n);                                                                         \
+        return hipGetLastError();                                                            \
+    }
+    APO_TILE_SHAPES(APO_TILE_PERSIST)
+#undef APO_TILE_PERSIST
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int NPMAX>

@@ -12,4 +12,9 @@ hipError_t launch_tile_batch_f32(const Params &proto, const BatchLaunch &b, hipS
                          : launch_tile_t<float, kMaxNp>(proto, 0, s, &b);
 }
 
+hipError_t launch_tile_persist_f32(const Params &p, int t0, int n, hipStream_t s) {
+    return p.np == 1 ? launch_tile_persist_t<float, 1>(p, t0, n, s)
+                     : launch_tile_persist_t<float, kMaxNp>(p, t0, n, s);
+}
+
 }  // namespace apok

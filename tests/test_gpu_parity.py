@@ -194,12 +194,24 @@ def test_graph_replay_equals_single_steps_and_is_deterministic():
         assert a[2] == b[2] == c[2] == 40
 
 
+_OTSU_HIST = gen.histogram_of(gen.blob_image(128, 128, seed=6))
+
+
 @pytest.mark.parametrize("kw", [
     dict(dim=10, pop=32, kind="rastrigin", precision="fp64", max_iter=60),
     dict(dim=16, pop=64, kind="rosenbrock", precision="fp32", max_iter=40, pf_max=0.5),
     dict(dim=10, pop=50, kind="sphere", precision="fp64", max_iter=30, np_pairs=3),
     dict(dim=3, pop=4, kind="ackley", precision="fp32", max_iter=25, pf_max=1.0),
-], ids=["c1_fp64", "rosenbrock_fp32_full_wg", "sphere_np3", "tiny_all_dr"])
+    # tiled runs one wide tile holds
+    dict(dim=1, pop=100, kind="otsu", precision="fp64", max_iter=50, lb=0.0, ub=255.0,
+         hist=_OTSU_HIST),
+    dict(dim=4, pop=128, kind="kapur", precision="fp32", max_iter=20, lb=0.0, ub=255.0,
+         hist=_OTSU_HIST, pf_max=0.5),
+    dict(dim=12, pop=90, kind="rastrigin", rotated=True, precision="fp32", max_iter=30),
+    dict(dim=10, pop=40, kind="rosenbrock", rotated=True, precision="fp64", max_iter=20,
+         np_pairs=2),
+], ids=["c1_fp64", "rosenbrock_fp32_full_wg", "sphere_np3", "tiny_all_dr", "otsu_table_shape",
+        "kapur_k4_full_tile", "rotated_rastrigin_fp32", "rotated_rosenbrock_fp64_np2"])
 def test_persistent_run_equals_single_steps(kw):
     """Runs whose whole population fits one workgroup take the persistent
     form in apo_run (one launch for all iterations); the state after it is
