@@ -845,7 +845,7 @@ int apo_run(apo_t *h, int32_t iters) {
     if (h->poisoned) return APO_E_DEVICE;
     int32_t n = h->T - h->t;
     if (iters < n) n = iters;
-    if (apok::persist_form(h->p)) {
+    if (apok::persist_form(h->p, h->fp64)) {
         // the whole run in one workgroup: all n iterations in one launch
         if (n <= 0) return 0;
         APO_HIP(h, apok::launch_persist(h->p, h->fp64, h->t, n, h->stream));

@@ -82,7 +82,7 @@ struct Params {
     const double *p_dr;   // [pop] Eq. (13) for rank r + 1
     const void *lb, *ub, *shift;   // [Dp]
     const void *rotp;     // packed MFMA B fragments of M^T
-    const double *htab;   // histogram prefix tables (4 x 257)
+    const double *htab;   // histogram prefix tables (3 x 257: P, S, M1)
     void *trY;            // [pop][Dp]
     void *trF;            // [pop]
     int32_t *trOp;        // [pop]
@@ -199,11 +199,12 @@ inline size_t step_lds_bytes(const Params &p, bool fp64) {
 // Whether a run takes the persistent form of apo_run (one workgroup running
 // every iteration): the whole population in one workgroup of the step --
 // the elementwise step's 256 threads, or one tile -- and a sort of one LDS
-// workgroup.
-inline bool persist_form(const Params &p) {
+// workgroup; the elementwise form also holds the run's LDS image.
+inline bool persist_form(const Params &p, bool fp64) {
     if (p.gemm || p.pop > 256) return false;
     if (tile_form(p)) return p.pop <= tile_rows(p);
-    return (long long)p.pop * lanes_for_dim(p.dim) <= 256;
+    return (long long)p.pop * lanes_for_dim(p.dim) <= 256 &&
+           persist_image(p.pop, p.Dp, fp64 ? 8 : 4, false).total + kPersistStaticLds <= kLdsLimit;
 }
 
 // Instantiation key: precision, form, lanes, chunks, rows and whether np > 1

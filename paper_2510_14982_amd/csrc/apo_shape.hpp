@@ -105,6 +105,41 @@ inline bool tile_shape_ok(int dim, int G, int NCH, int TM, int es) {
     return tile_dynamic_lds(dim, TM, es) + tile_static_lds(G, NCH, TM, es) <= kLdsLimit;
 }
 
+// LDS image of a run in the persistent form of apo_run (elementwise step),
+// which keeps the run's state there for the whole launch: both position
+// buffers [pop][Dp], fitness by id and by rank, the order and the Dr flags,
+// and the read-only per-run tables the iterations read (p_dr by rank,
+// bounds, shift and, for the thresholding objectives, the 3 x 257 histogram
+// tables).  Byte offsets
+// from the image's base, each 16-byte aligned.
+struct PersistImage {
+    size_t x0, x1, f, fs, perm, drf, pdr, lb, ub, sh, htab, total;
+};
+
+APO_HD inline PersistImage persist_image(int pop, int Dp, int es, bool hist) {
+    PersistImage m;
+    size_t o = 0;
+    const size_t xb = ((size_t)pop * Dp * es + 15) / 16 * 16;
+    const size_t fb = ((size_t)pop * es + 15) / 16 * 16, db = ((size_t)Dp * es + 15) / 16 * 16;
+    m.x0 = o; o += xb;
+    m.x1 = o; o += xb;
+    m.f = o; o += fb;
+    m.fs = o; o += fb;
+    m.perm = o; o += ((size_t)pop * 4 + 15) / 16 * 16;
+    m.drf = o; o += ((size_t)pop + 15) / 16 * 16;
+    m.pdr = o; o += ((size_t)pop * 8 + 15) / 16 * 16;
+    m.lb = o; o += db;
+    m.ub = o; o += db;
+    m.sh = o; o += db;
+    m.htab = o; o += hist ? (size_t)3 * 257 * 8 : 0;
+    m.total = o;
+    return m;
+}
+
+// Static LDS of the persistent form's sort (the LDS form: 1024 keys and the
+// iteration's subset keys) and a margin for the elementwise step's masks.
+constexpr size_t kPersistStaticLds = 16384;
+
 // Lanes per protozoan a run takes inside a batch (0: the dimension's own
 // count), with one row per lane group.  Rotated separable objectives take
 // four lanes up to 64 dimensions and eight up to 128 (64- or 128-row tiles,

@@ -137,7 +137,8 @@ __device__ __forceinline__ void open_iteration(const Params &p, int t, uint32_t 
 constexpr int kRankSmall = kRankLdsMax;
 
 template <typename T>
-__device__ __forceinline__ void rank_small_body(const Params &p, int blk, int t_open = 0) {
+__device__ __forceinline__ void rank_small_body(const Params &p, int blk, int t_open = 0,
+                                                bool publish = true) {
     __shared__ uint64_t s_k[kRankSmall];
     __shared__ uint32_t s_keys[24];
     __shared__ int32_t s_mdr;
@@ -175,7 +176,7 @@ __device__ __forceinline__ void rank_small_body(const Params &p, int blk, int t_
         for (int q = 0; q < 24; ++q) drs.k[q] = s_keys[q];
         p.drf[rank] = subset_has(drs, (uint32_t)rank, (uint32_t)s_mdr) ? 1 : 0;
     }
-    if (blk == 0 && tid == 64) {   // publish the iteration for the step
+    if (publish && blk == 0 && tid == 64) {   // publish the iteration for the step
         p.ctrl->m_dr = s_mdr;
         p.ctrl->p_ah = p.p_ah[t];
         p.ctrl->fscale = p.fscale[t];
@@ -510,9 +511,9 @@ __device__ __forceinline__ void step_elem_body(const Params &p, int init, int bl
     const Iter it = itp ? *itp : load_iter(p, init);
     const int t = it.t;
     const int src = (t + 1) & 1, dst = t & 1;
-    const T *Xc = (const T *)p.X[src];
+    const T *Xc = (const T *)(src ? p.X[1] : p.X[0]);   // (no dynamic index: p may be a local)
     const T *Fc = (const T *)p.Fs;   // old fitness, in rank order
-    T *Xn = (T *)p.X[dst];
+    T *Xn = (T *)(dst ? p.X[1] : p.X[0]);
     T *Fn = (T *)p.F;
 
     constexpr int MW = (4 * G * NCH + 31) / 32;
@@ -611,7 +612,7 @@ __device__ __forceinline__ void step_elem_body(const Params &p, int init, int bl
         if (d0 < D) store4(row + d0, accept ? ys[ch] : xs[ch]);
     }
     if (lane == 0) Fn[c.id] = accept ? fnew : c.fold;
-    if (!init && blk == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
+    if (!init && !itp && blk == 0 && threadIdx.x == 0) p.ctrl->t = t;   // iteration closed
     if (p.trace && !init) {
         T *ty = (T *)p.trY + (size_t)c.id * Dp;
 #pragma unroll
@@ -640,36 +641,106 @@ __global__ __launch_bounds__(256) void step_elem_batch(const Params *runs, const
     step_elem_body<T, G, NCH, NPMAX>(runs[b.x], init, b.y);
 }
 
-// Persistent form of a run whose whole population one workgroup of the
-// elementwise step holds (ps G <= 256 lanes, ps <= 256): a single workgroup
+// ---------------------------------------------------------------------------
+// Persistent form (apo_run of a run that one workgroup holds): one workgroup
 // runs n iterations, each the sort (LDS form, the whole population) and the
-// step, separated by workgroup barriers only -- the barriers also make each
-// phase's global writes (order, fitness by rank, Dr flags; rows and fitness)
-// visible to the next phase, all of it on one CU.  The device code is the
+// step, separated by workgroup barriers only.  The run's state and the
+// read-only tables its iterations read are copied into an LDS image at entry
+// (PersistImage) and the parameters' pointers redirected there, so an
+// iteration touches no global memory apart from the trace; the state is
+// copied back at exit and the control block written as the last iteration's
+// sort and step would leave it.  The device code of sort and step is the
 // two-kernel iteration's, so the results are the same bit for bit.
+// ---------------------------------------------------------------------------
+template <typename U>
+__device__ __forceinline__ void block_copy(U *dst, const U *src, size_t n) {
+    for (size_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+template <typename T>
+__device__ __forceinline__ Params persist_enter(const Params &p, unsigned char *img) {
+    const bool hist = p.kind == K_KAPUR || p.kind == K_OTSU;
+    const PersistImage m = persist_image(p.pop, p.Dp, (int)sizeof(T), hist);
+    const size_t rows = (size_t)p.pop * p.Dp;
+    Params q = p;
+    q.X[0] = img + m.x0;
+    q.X[1] = img + m.x1;
+    q.F = img + m.f;
+    q.Fs = img + m.fs;
+    q.perm = (int32_t *)(img + m.perm);
+    q.drf = img + m.drf;
+    q.p_dr = (const double *)(img + m.pdr);
+    q.lb = img + m.lb;
+    q.ub = img + m.ub;
+    q.shift = img + m.sh;
+    block_copy((T *)(img + m.x0), (const T *)p.X[0], rows);
+    block_copy((T *)(img + m.x1), (const T *)p.X[1], rows);
+    block_copy((T *)(img + m.f), (const T *)p.F, (size_t)p.pop);
+    block_copy((double *)(img + m.pdr), p.p_dr, (size_t)p.pop);
+    block_copy((T *)(img + m.lb), (const T *)p.lb, (size_t)p.Dp);
+    block_copy((T *)(img + m.ub), (const T *)p.ub, (size_t)p.Dp);
+    block_copy((T *)(img + m.sh), (const T *)p.shift, (size_t)p.Dp);
+    if (hist) {
+        q.htab = (const double *)(img + m.htab);
+        block_copy((double *)(img + m.htab), p.htab, (size_t)3 * 257);
+    }
+    return q;
+}
+
+template <typename T>
+__device__ __forceinline__ void persist_leave(const Params &p, const Params &q) {
+    const size_t rows = (size_t)p.pop * p.Dp;
+    block_copy((T *)p.X[0], (const T *)q.X[0], rows);
+    block_copy((T *)p.X[1], (const T *)q.X[1], rows);
+    block_copy((T *)p.F, (const T *)q.F, (size_t)p.pop);
+    block_copy((T *)p.Fs, (const T *)q.Fs, (size_t)p.pop);
+    block_copy(p.perm, (const int32_t *)q.perm, (size_t)p.pop);
+    block_copy(p.drf, (const uint8_t *)q.drf, (size_t)p.pop);
+}
+
+__device__ __forceinline__ Iter iter_at(const Params &p, int t) {
+    Iter it;
+    it.t = t;
+    it.p_ah = p.p_ah[t];
+    it.fscale = p.fscale[t];
+    it.cnear = p.cnear[t];
+    return it;
+}
+
 template <typename T, int G, int NCH, int NPMAX>
 __global__ __launch_bounds__(256) void run_elem_persist(Params p, int t0, int n) {
+    extern __shared__ __align__(16) unsigned char pdyn[];
+    const Params q = persist_enter<T>(p, pdyn);
+    Iter it = iter_at(p, t0 + 1);
+    __syncthreads();
     for (int k = 1; k <= n; ++k) {
         const int t = t0 + k;
-        rank_small_body<T>(p, 0, t);
+        const Iter cur = it;
+        if (k < n) it = iter_at(p, t + 1);   // the next iteration's scalars, ahead
+        rank_small_body<T>(q, 0, t, k == n);
         __syncthreads();
-        Iter it;
-        it.t = t;
-        it.p_ah = p.p_ah[t];
-        it.fscale = p.fscale[t];
-        it.cnear = p.cnear[t];
-        step_elem_body<T, G, NCH, NPMAX>(p, 0, 0, &it);
+        step_elem_body<T, G, NCH, NPMAX>(q, 0, 0, &cur);
         __syncthreads();
     }
+    persist_leave<T>(p, q);
+    if (threadIdx.x == 0) p.ctrl->t = t0 + n;   // iterations closed
 }
 
 template <typename T, int NPMAX>
 hipError_t launch_persist_t(const Params &p, int t0, int n, hipStream_t s) {
     const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
-    if (!persist_form(p) || n < 1) return hipErrorInvalidValue;
+    const bool fp64 = sizeof(T) == 8;
+    if (!persist_form(p, fp64) || n < 1) return hipErrorInvalidValue;
+    const size_t lds = persist_image(p.pop, p.Dp, (int)sizeof(T), false).total;
 #define APO_PERSIST(GG, CC)                                                                  \
     if (G == GG && NCH == CC) {                                                              \
-        launch_k(p, run_elem_persist<T, GG, CC, NPMAX>, dim3(1), dim3(256), 0, s, p, t0, n); \
+        const void *fn = (const void *)run_elem_persist<T, GG, CC, NPMAX>;                   \
+        if (lds > 65536) {                                                                   \
+            const hipError_t ea =                                                            \
+                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+            if (ea != hipSuccess) return ea;                                                 \
+        }                                                                                    \
+        launch_k(p, run_elem_persist<T, GG, CC, NPMAX>, dim3(1), dim3(256), lds, s, p, t0, n); \
         return hipGetLastError();                                                            \
     }
     APO_ELEM_SHAPES(APO_PERSIST)
@@ -796,9 +867,9 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
     const Iter it = itp ? *itp : load_iter(p, init);
     const int t = it.t;
     const int src = (t + 1) & 1, dst = t & 1;
-    const T *Xc = (const T *)p.X[src];
+    const T *Xc = (const T *)(src ? p.X[1] : p.X[0]);   // (no dynamic index: p may be a local)
     const T *Fc = (const T *)p.Fs;   // old fitness, in rank order
-    T *Xn = (T *)p.X[dst];
+    T *Xn = (T *)(dst ? p.X[1] : p.X[0]);
     T *Fn = (T *)p.F;
     const T *o = (const T *)p.shift;
     const int r0 = blk * TM;
@@ -1062,21 +1133,18 @@ __global__ __launch_bounds__(512) void step_tile_batch(const Params *runs, const
 }
 
 // Persistent form of a tiled run whose population one tile holds (ps <= TM,
-// ps <= 256): as run_elem_persist, one workgroup runs n iterations of the
-// sort (LDS form; its threads past 256 take no part) and the tiled step,
-// separated by workgroup barriers; the iteration is closed in the control
-// block at the end.
+// ps <= 256): one workgroup runs n iterations of the sort (LDS form; its
+// threads past 256 take no part) and the tiled step, separated by workgroup
+// barriers, on the run's global buffers (the step's own LDS leaves no room
+// for the run's image; the global form measured faster here as well); the
+// iterations are closed in the control block at the end.
 template <typename T, int G, int NCH, int NPMAX, int TM>
 __global__ __launch_bounds__(512) void run_tile_persist(Params p, int t0, int n) {
     for (int k = 1; k <= n; ++k) {
         const int t = t0 + k;
         rank_small_body<T>(p, 0, t);
         __syncthreads();
-        Iter it;
-        it.t = t;
-        it.p_ah = p.p_ah[t];
-        it.fscale = p.fscale[t];
-        it.cnear = p.cnear[t];
+        const Iter it = iter_at(p, t);
         step_tile_body<T, G, NCH, NPMAX, TM>(p, 0, 0, &it);
         __syncthreads();
     }
@@ -1121,8 +1189,9 @@ hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLa
 template <typename T, int NPMAX>
 hipError_t launch_tile_persist_t(const Params &p, int t0, int n, hipStream_t s) {
     const int G = tile_lanes(p), NCH = tile_chunks(p), TMr = tile_rows(p);
-    if (!persist_form(p) || n < 1 || NCH < 0) return hipErrorInvalidValue;
-    const size_t lds = tile_lds_bytes(p, sizeof(T) == 8);
+    const bool fp64 = sizeof(T) == 8;
+    if (!persist_form(p, fp64) || n < 1 || NCH < 0) return hipErrorInvalidValue;
+    const size_t lds = tile_lds_bytes(p, fp64);
 #define APO_TILE_PERSIST(GG, CC, TMM)                                                        \
     if (G == GG && NCH == CC && TMr == TMM) {                                                \
         const void *fn = (const void *)run_tile_persist<T, GG, CC, NPMAX, TMM>;              \
