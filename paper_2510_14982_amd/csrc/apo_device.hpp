@@ -165,38 +165,73 @@ __device__ __forceinline__ uint32_t subset_pi(const Subset &s, uint32_t x) {
 // below n along the pass order p(0), p(1), ..., p(2^b - 1) (one pass, no
 // cycle walking).  Built by the G lanes of one group (lanes lane0 ..
 // lane0 + G - 1 of one wavefront, all active): each round the lanes take
-// G consecutive positions, and a ballot gives each valid lane the number
-// of valid values before it, so the first m are kept without any lane
-// waiting on another.  For m > n / 2 the last n - m values (scanning from
-// the end) are cleared from an all-ones mask instead.
+// U G consecutive positions (lane l holds positions base + j G + l, j < U,
+// whose U passes are independent chains evaluated together), and, position
+// block by block in order, a ballot gives each valid lane the number of
+// valid values before it, so the first m are kept without any lane waiting
+// on another.  For m > n / 2 the last n - m values (scanning from the end)
+// are cleared from an all-ones mask instead.  U = 4 (`ilp`) shortens the
+// chain where many rounds are needed or latency alone counts; U = 1 spends
+// no passes past the last one needed, the choice where issue slots count.
+template <int G, int U, int ROUNDS, bool TABLE>
+__device__ __forceinline__ void subset_mask_scan(const Subset &s, uint32_t cnt, bool comp,
+                                                 uint32_t *words, int lane, int lane0) {
+    const uint32_t n = s.n, dom = s.walk;
+    const uint64_t group = (G >= 64 ? ~0ull : ((1ull << G) - 1ull)) << lane0;
+    const uint64_t below = (1ull << (lane0 + lane)) - 1ull;   // lanes before this one
+    uint32_t taken = 0;
+    for (uint32_t base = 0; taken < cnt && base < dom; base += U * G) {
+        uint32_t y[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t pos = base + (uint32_t)(j * G + lane);
+            const uint32_t x = pos < dom ? (comp ? dom - 1u - pos : pos) : 0u;
+            y[j] = feistel_fwd<ROUNDS, TABLE>(s.k, s.a0, s.c0, x);
+            if (pos >= dom) y[j] = 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const bool valid = y[j] < n;
+            const uint64_t vb = __ballot(valid) & group;
+            const uint32_t before = (uint32_t)__popcll(vb & below);
+            if (valid && taken + before < cnt) {
+                if (comp)
+                    atomicAnd(&words[y[j] >> 5], ~(1u << (y[j] & 31)));
+                else
+                    atomicOr(&words[y[j] >> 5], 1u << (y[j] & 31));
+            }
+            taken += (uint32_t)__popcll(vb);
+        }
+    }
+}
+
+template <int G, int U>
+__device__ __forceinline__ void subset_mask_rounds(const Subset &s, uint32_t cnt, bool comp,
+                                                   uint32_t *words, int lane, int lane0) {
+    switch (s.rounds) {
+    case 24: subset_mask_scan<G, U, 24, true>(s, cnt, comp, words, lane, lane0); break;
+    case 20: subset_mask_scan<G, U, 20, true>(s, cnt, comp, words, lane, lane0); break;
+    case 16: subset_mask_scan<G, U, 16, false>(s, cnt, comp, words, lane, lane0); break;
+    case 12: subset_mask_scan<G, U, 12, false>(s, cnt, comp, words, lane, lane0); break;
+    default: subset_mask_scan<G, U, 8, false>(s, cnt, comp, words, lane, lane0); break;
+    }
+}
+
 template <int G>
 __device__ __forceinline__ void subset_mask_group(const Subset &s, uint32_t m, uint32_t *words,
-                                                  int nwords, int lane, int lane0) {
-    const uint32_t n = s.n, dom = s.walk;
+                                                  int nwords, int lane, int lane0,
+                                                  bool ilp = false) {
+    const uint32_t n = s.n;
     const bool comp = m > n - m;
     const uint32_t cnt = comp ? n - m : m;
     for (int w = lane; w < nwords; w += G) words[w] = comp ? 0xFFFFFFFFu : 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint64_t group = (G >= 64 ? ~0ull : ((1ull << G) - 1ull)) << lane0;
-    const uint64_t below = (1ull << (lane0 + lane)) - 1ull;   // lanes before this one
-    uint32_t taken = 0;
-    for (uint32_t base = 0; taken < cnt && base < dom; base += G) {
-        const uint32_t pos = base + (uint32_t)lane;
-        uint32_t y = 0xFFFFFFFFu;
-        if (pos < dom) y = subset_pass(s, comp ? dom - 1u - pos : pos);
-        const bool valid = y < n;
-        const uint64_t vb = __ballot(valid) & group;
-        const uint32_t before = (uint32_t)__popcll(vb & below);
-        if (valid && taken + before < cnt) {
-            if (comp)
-                atomicAnd(&words[y >> 5], ~(1u << (y & 31)));
-            else
-                atomicOr(&words[y >> 5], 1u << (y & 31));
-        }
-        taken += (uint32_t)__popcll(vb);
-    }
+    if (ilp)
+        subset_mask_rounds<G, 4>(s, cnt, comp, words, lane, lane0);
+    else
+        subset_mask_rounds<G, 1>(s, cnt, comp, words, lane, lane0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -372,9 +372,12 @@ template <typename T, int NPMAX, int G>
 __device__ __forceinline__ void plan_mask(const Params &p, Plan<T, NPMAX> &c, uint32_t *mwords,
                                           int lane) {
     c.mw = mwords;
+    // four positions a lane per round where the scan spans eight or more
+    // rounds of G positions, or where the run is one workgroup (latency only)
+    const bool ilp = c.mask.walk >= 8u * G || (long long)p.pop * G <= 256;
     if (c.op != OP_DORMANCY)
         subset_mask_group<G>(c.mask, c.m, mwords, (p.dim + 31) / 32, lane,
-                             (int)(threadIdx.x & 63) & ~(G - 1));
+                             (int)(threadIdx.x & 63) & ~(G - 1), ilp);
 }
 
 // Rows a lane reads for its NCH chunks of 4 coordinates, loaded before the

@@ -65,7 +65,14 @@ int main(int argc, char **argv) {
             apok::Subset s;
             apok::subset_init(s, k, n);
             const int nw = (int)((n + 31) / 32);
-            apok::subset_mask_group<1>(s, m, words, nw, 0, 0);
+            // both scan forms (one position a round, and four) give the same set
+            static unsigned words4[1 << 11];
+            apok::subset_mask_group<1>(s, m, words, nw, 0, 0, false);
+            apok::subset_mask_group<1>(s, m, words4, nw, 0, 0, true);
+            if (std::memcmp(words, words4, (size_t)nw * 4) != 0) {
+                std::printf("scan forms differ\n");
+                return 1;
+            }
             for (unsigned x = 0; x < n; ++x)
                 if ((words[x >> 5] >> (x & 31)) & 1u) std::printf("%u ", x);
             std::printf("\n");
