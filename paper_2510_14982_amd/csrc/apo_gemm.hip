@@ -208,9 +208,22 @@ __global__ __launch_bounds__(256) void gemm_obj_f32(GemmRun g) {
     extern __shared__ __align__(16) unsigned char gsm[];
     unsigned char *sA = gsm, *sB = gsm + kGM * kGLds;
     const int nrows = g.list ? *g.count : g.rows;
-    const int m0 = blockIdx.y * kGM;
+    // the column blocks of a row block on one XCD (workgroup b runs on XCD
+    // b mod 8), so the block's A rows are fetched from HBM once into its L2
+    const int nM = (g.rows + kGM - 1) / kGM, nN = g.Np / kGN;
+    const int b = blockIdx.x;
+    int rb, nb;
+    if ((nM & 7) == 0) {
+        const int x = b & 7, idx = b >> 3;
+        rb = (idx / nN) * 8 + x;
+        nb = idx % nN;
+    } else {
+        rb = b / nN;
+        nb = b % nN;
+    }
+    const int m0 = rb * kGM;
     if (m0 >= nrows) return;   // the whole workgroup: no barrier is skipped
-    const int n0 = blockIdx.x * kGN;
+    const int n0 = nb * kGN;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
     const int lr = tid >> 1, lh = tid & 1;                  // A loader: row, half chunk
     const int br = tid / kGBT, bq = tid % kGBT;              // M loader: row, part
@@ -692,7 +705,7 @@ static hipError_t launch_gemm_t(const Params &p, const GemmRun &g, bool bf16, hi
                                               hipFuncAttributeMaxDynamicSharedMemorySize,
                                               (int)kGemmLds);
     if (ea != hipSuccess) return ea;
-    const dim3 grid((unsigned)(g.Np / kGN), (unsigned)((g.rows + kGM - 1) / kGM)), block(256);
+    const dim3 grid((unsigned)((g.Np / kGN) * ((g.rows + kGM - 1) / kGM))), block(256);
     launch_k(p, gemm_obj_f32<KIND>, grid, block, kGemmLds, s, g);
     return hipGetLastError();
 }
