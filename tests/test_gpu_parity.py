@@ -202,6 +202,9 @@ _OTSU_HIST = gen.histogram_of(gen.blob_image(128, 128, seed=6))
     dict(dim=16, pop=64, kind="rosenbrock", precision="fp32", max_iter=40, pf_max=0.5),
     dict(dim=10, pop=50, kind="sphere", precision="fp64", max_iter=30, np_pairs=3),
     dict(dim=3, pop=4, kind="ackley", precision="fp32", max_iter=25, pf_max=1.0),
+    # one protozoan a wavefront; the LDS image above 64 KiB (D 1000, binary64)
+    dict(dim=1000, pop=4, kind="sphere", precision="fp64", max_iter=12),
+    dict(dim=200, pop=4, kind="rastrigin", precision="fp32", max_iter=20, pf_max=0.5),
     # tiled runs one wide tile holds
     dict(dim=1, pop=100, kind="otsu", precision="fp64", max_iter=50, lb=0.0, ub=255.0,
          hist=_OTSU_HIST),
@@ -210,7 +213,8 @@ _OTSU_HIST = gen.histogram_of(gen.blob_image(128, 128, seed=6))
     dict(dim=12, pop=90, kind="rastrigin", rotated=True, precision="fp32", max_iter=30),
     dict(dim=10, pop=40, kind="rosenbrock", rotated=True, precision="fp64", max_iter=20,
          np_pairs=2),
-], ids=["c1_fp64", "rosenbrock_fp32_full_wg", "sphere_np3", "tiny_all_dr", "otsu_table_shape",
+], ids=["c1_fp64", "rosenbrock_fp32_full_wg", "sphere_np3", "tiny_all_dr", "d1000_lds_64k_plus",
+        "d200_one_wave_each", "otsu_table_shape",
         "kapur_k4_full_tile", "rotated_rastrigin_fp32", "rotated_rosenbrock_fp64_np2"])
 def test_persistent_run_equals_single_steps(kw):
     """Runs whose whole population fits one workgroup take the persistent
@@ -232,6 +236,9 @@ def test_persistent_run_equals_single_steps(kw):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
         assert a[2] == b[2] == c[2] == T
+        # the last iteration's trace (candidates, their fitness, operations, order)
+        for u, v in zip(g1.get_trace(), g2.get_trace()):
+            assert np.array_equal(u, v)
         assert g1.run(3) == 0
         x1, f1, e1 = g1.best()
         x2, f2, e2 = g2.best()
