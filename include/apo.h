@@ -140,10 +140,12 @@ int apo_step(apo_t *h);
  * graphs, captured on the first call (apo_run(h, 0) captures them and
  * executes nothing, so a later timed call does not include the capture).
  * A run whose whole population fits one workgroup of the step (elementwise
- * objectives with pop x lanes <= 256, pop <= 256; e.g. pop 32 at dim 10)
- * instead runs all its iterations in one single-workgroup launch (the
- * persistent form: sort and step separated by workgroup barriers); the
- * results are the same bit for bit. */
+ * objectives with pop x lanes <= 256, pop <= 256, e.g. pop 32 at dim 10; or
+ * a rotated or thresholding run that one wide tile holds, e.g. Otsu at pop
+ * 100, dim 1) instead runs all its iterations in one single-workgroup launch
+ * (the persistent form: sort and step separated by workgroup barriers; the
+ * elementwise form keeps the run's state in LDS for the launch); the results
+ * are the same bit for bit. */
 int apo_run(apo_t *h, int32_t iters);
 
 /* The best protozoan (lowest fitness; NaN never wins; lowest id on ties):
