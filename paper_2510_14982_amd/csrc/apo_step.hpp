@@ -849,7 +849,10 @@ __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
 // `itp`: the iteration and its scalars when the caller knows them; nullptr
 // reads them from the control block, and workgroup 0 then closes the
 // iteration there.
-template <typename T, int G, int NCH, int NPMAX, int TM>
+// THR: the run's objective is known to be a thresholding one (no matrix
+// phase compiled in; the persistent form of such runs, where registers are
+// short).
+template <typename T, int G, int NCH, int NPMAX, int TM, bool THR = false>
 __device__ __forceinline__ void step_tile_body(const Params &p, int init, int blk,
                                                const Iter *itp = nullptr) {
     constexpr int NT = 512, GROUPS = NT / G, RB = TM / 16;
@@ -886,7 +889,7 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
     {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
         const T *B = (const T *)p.rotp;
-        if (p.rotated && p.Ks == PRE && wave < RB * p.Nt) {
+        if (!THR && p.rotated && p.Ks == PRE && wave < RB * p.Nt) {
             const int nt0 = wave % p.Nt;
 #pragma unroll
             for (int ks = 0; ks < PRE; ++ks) bpre[ks] = B[((size_t)ks * p.Nt + nt0) * 64 + l];
@@ -959,11 +962,12 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
     }
     __syncthreads();
 
-    const bool thresholds = p.kind == K_KAPUR || p.kind == K_OTSU;
+    const bool thresholds = THR || p.kind == K_KAPUR || p.kind == K_OTSU;
+    const bool rot = !THR && p.rotated;
     // separable objectives of a rotated problem are summed from the matrix
     // core accumulators in phase 2
-    const bool separable = p.rotated && !thresholds && p.kind != K_ROSENBROCK;
-    if (p.rotated) {
+    const bool separable = rot && !thresholds && p.kind != K_ROSENBROCK;
+    if (rot) {
         // phase 2: Z = (Y - o) M^T on the matrix cores.  Fragment layout of
         // v_mfma 16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
         // the output row of (lane, element) is given by mfma_out_row.
@@ -1055,10 +1059,10 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
             T s1 = T(0), s2 = T(0);
             if (s_id[row] >= 0) {
                 for (int d = lane; d < D; d += G) {
-                    const T z = p.rotated ? Zs[row * LZ + d] : As[row * LS + d];
+                    const T z = rot ? Zs[row * LZ + d] : As[row * LS + d];
                     if (p.kind == K_ROSENBROCK) {
                         if (d + 1 < D) {
-                            const T zn = p.rotated ? Zs[row * LZ + d + 1] : As[row * LS + d + 1];
+                            const T zn = rot ? Zs[row * LZ + d + 1] : As[row * LS + d + 1];
                             const T a = z + T(1), b = zn + T(1);
                             s1 += T(100) * (b - a * a) * (b - a * a) + (a - T(1)) * (a - T(1));
                         }
@@ -1141,17 +1145,42 @@ __global__ __launch_bounds__(512) void step_tile_batch(const Params *runs, const
 // barriers, on the run's global buffers (the step's own LDS leaves no room
 // for the run's image; the global form measured faster here as well); the
 // iterations are closed in the control block at the end.
-template <typename T, int G, int NCH, int NPMAX, int TM>
+template <typename T, int G, int NCH, int NPMAX, int TM, bool THR>
 __global__ __launch_bounds__(512) void run_tile_persist(Params p, int t0, int n) {
     for (int k = 1; k <= n; ++k) {
         const int t = t0 + k;
         rank_small_body<T>(p, 0, t);
         __syncthreads();
         const Iter it = iter_at(p, t);
-        step_tile_body<T, G, NCH, NPMAX, TM>(p, 0, 0, &it);
+        step_tile_body<T, G, NCH, NPMAX, TM, THR>(p, 0, 0, &it);
         __syncthreads();
     }
     if (threadIdx.x == 0 && n > 0) p.ctrl->t = t0 + n;   // iterations closed
+}
+
+// The launch of one persistent shape: thresholding runs take the kernel
+// without the matrix phase where their shapes are (one chunk, at most 16
+// lanes: k <= 64 thresholds).
+template <typename T, int GG, int CC, int NPMAX, int TMM, bool THR>
+hipError_t launch_tile_persist_one(const Params &p, int t0, int n, size_t lds, hipStream_t s) {
+    const void *fn = (const void *)run_tile_persist<T, GG, CC, NPMAX, TMM, THR>;
+    if (lds > 65536) {
+        const hipError_t ea =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (ea != hipSuccess) return ea;
+    }
+    launch_k(p, run_tile_persist<T, GG, CC, NPMAX, TMM, THR>, dim3(1), dim3(512), lds, s, p, t0,
+             n);
+    return hipGetLastError();
+}
+
+template <typename T, int GG, int CC, int NPMAX, int TMM>
+hipError_t launch_tile_persist_shape(const Params &p, int t0, int n, size_t lds, hipStream_t s) {
+    if constexpr (CC == 1 && GG <= 16) {
+        if (p.kind == K_KAPUR || p.kind == K_OTSU)
+            return launch_tile_persist_one<T, GG, CC, NPMAX, TMM, true>(p, t0, n, lds, s);
+    }
+    return launch_tile_persist_one<T, GG, CC, NPMAX, TMM, false>(p, t0, n, lds, s);
 }
 
 
@@ -1196,17 +1225,8 @@ hipError_t launch_tile_persist_t(const Params &p, int t0, int n, hipStream_t s) 
     if (!persist_form(p, fp64) || n < 1 || NCH < 0) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(p, fp64);
 #define APO_TILE_PERSIST(GG, CC, TMM)                                                        \
-    if (G == GG && NCH == CC && TMr == TMM) {                                                \
-        const void *fn = (const void *)run_tile_persist<T, GG, CC, NPMAX, TMM>;              \
-        if (lds > 65536) {                                                                   \
-            const hipError_t ea =                                                            \
-                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-            if (ea != hipSuccess) return ea;                                                 \
-        }                                                                                    \
-        launch_k(p, run_tile_persist<T, GG, CC, NPMAX, TMM>, dim3(1), dim3(512), lds, s, p, t0, \
-                 n);                                                                         \
-        return hipGetLastError();                                                            \
-    }
+    if (G == GG && NCH == CC && TMr == TMM)                                                  \
+        return launch_tile_persist_shape<T, GG, CC, NPMAX, TMM>(p, t0, n, lds, s);
     APO_TILE_SHAPES(APO_TILE_PERSIST)
 #undef APO_TILE_PERSIST
     return hipErrorInvalidValue;
