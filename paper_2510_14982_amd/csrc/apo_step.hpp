@@ -1132,6 +1132,11 @@ template <typename T, int G, int NCH, int NPMAX, int TM>
 __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     step_tile_body<T, G, NCH, NPMAX, TM>(p, init, (int)blockIdx.x);
 }
+// The tiled step of a thresholding run (no matrix phase compiled in).
+template <typename T, int G, int NCH, int NPMAX, int TM>
+__global__ __launch_bounds__(512) void step_tile_thr(Params p, int init) {
+    step_tile_body<T, G, NCH, NPMAX, TM, true>(p, init, (int)blockIdx.x);
+}
 template <typename T, int G, int NCH, int NPMAX, int TM>
 __global__ __launch_bounds__(512) void step_tile_batch(const Params *runs, const int2 *blocks,
                                                        int init) {
@@ -1184,6 +1189,28 @@ hipError_t launch_tile_persist_shape(const Params &p, int t0, int n, size_t lds,
 }
 
 
+// A thresholding run's step on the kernel without the matrix phase, where its
+// shape has one (one chunk, at most 16 lanes); `done` false: not launched here.
+template <typename T, int GG, int CC, int NPMAX, int TMM>
+hipError_t launch_tile_thr(const Params &p, int init, dim3 grid, size_t lds, hipStream_t s,
+                           bool &done) {
+    done = false;
+    if constexpr (CC == 1 && GG <= 16) {
+        if (p.kind == K_KAPUR || p.kind == K_OTSU) {
+            done = true;
+            if (lds > 65536) {
+                const hipError_t ea =
+                    hipFuncSetAttribute((const void *)step_tile_thr<T, GG, CC, NPMAX, TMM>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (ea != hipSuccess) return ea;
+            }
+            launch_k(p, step_tile_thr<T, GG, CC, NPMAX, TMM>, grid, dim3(512), lds, s, p, init);
+            return hipGetLastError();
+        }
+    }
+    return hipSuccess;
+}
+
 // A launch of one handle (b == nullptr: grid of the run's own blocks, lds
 // from its shape) or of a batch (b: the runs of one kernel shape, `p` one
 // of them, lds the largest of theirs).
@@ -1205,11 +1232,16 @@ hipError_t launch_tile_t(const Params &p, int init, hipStream_t s, const BatchLa
                 hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
             if (ea != hipSuccess) return ea;                                                 \
         }                                                                                    \
-        if (b)                                                                               \
+        if (b) {                                                                             \
             hipLaunchKernelGGL((step_tile_batch<T, GG, CC, NPMAX, TMM>), grid, block, lds, s, \
                                b->runs, b->blocks, init);                                    \
-        else                                                                                 \
+        } else {                                                                             \
+            bool done;                                                                       \
+            const hipError_t et =                                                            \
+                launch_tile_thr<T, GG, CC, NPMAX, TMM>(p, init, grid, lds, s, done);         \
+            if (done) return et;                                                             \
             launch_k(p, step_tile<T, GG, CC, NPMAX, TMM>, grid, block, lds, s, p, init);     \
+        }                                                                                    \
         return hipGetLastError();                                                            \
     }
         APO_TILE_SHAPES(APO_TILE)
