@@ -196,6 +196,11 @@ inline size_t step_lds_bytes(const Params &p, bool fp64) {
     return tile_form(p) ? tile_lds_bytes(p, fp64) : 0;
 }
 
+// Dynamic LDS of the persistent elementwise launch: the run's LDS image.
+inline size_t persist_lds_bytes(const Params &p, bool fp64) {
+    return persist_image(p.pop, p.Dp, fp64 ? 8 : 4, p.kind == K_KAPUR || p.kind == K_OTSU).total;
+}
+
 // Whether a run takes the persistent form of apo_run (one workgroup running
 // every iteration): the whole population in one workgroup of the step --
 // the elementwise step's 256 threads, or one tile -- and a sort of one LDS
@@ -204,7 +209,7 @@ inline bool persist_form(const Params &p, bool fp64) {
     if (p.gemm || p.pop > 256) return false;
     if (tile_form(p)) return p.pop <= tile_rows(p);
     return (long long)p.pop * lanes_for_dim(p.dim) <= 256 &&
-           persist_image(p.pop, p.Dp, fp64 ? 8 : 4, false).total + kPersistStaticLds <= kLdsLimit;
+           persist_lds_bytes(p, fp64) + kPersistStaticLds <= kLdsLimit;
 }
 
 // Instantiation key: precision, form, lanes, chunks, rows and whether np > 1

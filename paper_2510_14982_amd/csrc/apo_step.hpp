@@ -734,7 +734,7 @@ hipError_t launch_persist_t(const Params &p, int t0, int n, hipStream_t s) {
     const int G = lanes_for_dim(p.dim), NCH = chunks_for_dim(p.dim);
     const bool fp64 = sizeof(T) == 8;
     if (!persist_form(p, fp64) || n < 1) return hipErrorInvalidValue;
-    const size_t lds = persist_image(p.pop, p.Dp, (int)sizeof(T), false).total;
+    const size_t lds = persist_lds_bytes(p, fp64);
 #define APO_PERSIST(GG, CC)                                                                  \
     if (G == GG && NCH == CC) {                                                              \
         const void *fn = (const void *)run_elem_persist<T, GG, CC, NPMAX>;                   \
