@@ -561,7 +561,7 @@ def main():
             "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
             "traffic": measured_traffic("c2") if args.workload == "c2" else None,
-            "kernel": "step_tile<float> (update + clamp + z = M(y-o) on MFMA + select)",
+            "kernel": "step_tile_sep<float> (update + clamp + z = M(y-o) on MFMA + select)",
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_alg,
             "hbm_frac_at_algorithmic_bytes": bytes_alg / (step_us * 1e-6) / 1e9 / PEAK_HBM_GBS}
     else:

@@ -849,12 +849,14 @@ __host__ __device__ inline int tile_row_stride(const Params &p, int es) {
 // `itp`: the iteration and its scalars when the caller knows them; nullptr
 // reads them from the control block, and workgroup 0 then closes the
 // iteration there.
-// THR: the run's objective is known to be a thresholding one (no matrix
-// phase compiled in; the persistent form of such runs, where registers are
-// short).
-template <typename T, int G, int NCH, int NPMAX, int TM, bool THR = false>
+// FORM: what the objective is known to be at compile time -- 0 any (read
+// from p), 1 a thresholding one (no matrix phase compiled in), 2 a rotated
+// separable one (Sphere, Rastrigin, Ackley: no Rosenbrock or thresholding
+// phases compiled in).
+template <typename T, int G, int NCH, int NPMAX, int TM, int FORM = 0>
 __device__ __forceinline__ void step_tile_body(const Params &p, int init, int blk,
                                                const Iter *itp = nullptr) {
+    constexpr bool THR = FORM == 1, SEP = FORM == 2;
     constexpr int NT = 512, GROUPS = NT / G, RB = TM / 16;
     static_assert(TM % 16 == 0 && TM % (NT / 32) == 0, "row blocks of 16; teams of 32 lanes");
     extern __shared__ __align__(16) unsigned char smem[];
@@ -889,7 +891,7 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
     {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
         const T *B = (const T *)p.rotp;
-        if (!THR && p.rotated && p.Ks == PRE && wave < RB * p.Nt) {
+        if ((SEP || (!THR && p.rotated)) && p.Ks == PRE && wave < RB * p.Nt) {
             const int nt0 = wave % p.Nt;
 #pragma unroll
             for (int ks = 0; ks < PRE; ++ks) bpre[ks] = B[((size_t)ks * p.Nt + nt0) * 64 + l];
@@ -962,11 +964,11 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
     }
     __syncthreads();
 
-    const bool thresholds = THR || p.kind == K_KAPUR || p.kind == K_OTSU;
-    const bool rot = !THR && p.rotated;
+    const bool thresholds = THR || (!SEP && (p.kind == K_KAPUR || p.kind == K_OTSU));
+    const bool rot = SEP || (!THR && p.rotated);
     // separable objectives of a rotated problem are summed from the matrix
     // core accumulators in phase 2
-    const bool separable = rot && !thresholds && p.kind != K_ROSENBROCK;
+    const bool separable = SEP || (rot && !thresholds && p.kind != K_ROSENBROCK);
     if (rot) {
         // phase 2: Z = (Y - o) M^T on the matrix cores.  Fragment layout of
         // v_mfma 16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
@@ -1001,7 +1003,7 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
                     for (int u = 0; u < 8; ++u) acc = mfma16x16x4(a[u], b[u], acc);
                 }
             }
-            if (p.kind == K_ROSENBROCK) {
+            if (!SEP && p.kind == K_ROSENBROCK) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     Zs[(16 * rb + mfma_out_row<T>(l, v)) * LZ + 16 * nt + (l & 15)] = acc[v];
@@ -1132,10 +1134,15 @@ template <typename T, int G, int NCH, int NPMAX, int TM>
 __global__ __launch_bounds__(512) void step_tile(Params p, int init) {
     step_tile_body<T, G, NCH, NPMAX, TM>(p, init, (int)blockIdx.x);
 }
-// The tiled step of a thresholding run (no matrix phase compiled in).
+// The tiled step of a thresholding run (no matrix phase compiled in), and
+// of a rotated separable one (no Rosenbrock or thresholding phases).
 template <typename T, int G, int NCH, int NPMAX, int TM>
 __global__ __launch_bounds__(512) void step_tile_thr(Params p, int init) {
-    step_tile_body<T, G, NCH, NPMAX, TM, true>(p, init, (int)blockIdx.x);
+    step_tile_body<T, G, NCH, NPMAX, TM, 1>(p, init, (int)blockIdx.x);
+}
+template <typename T, int G, int NCH, int NPMAX, int TM>
+__global__ __launch_bounds__(512) void step_tile_sep(Params p, int init) {
+    step_tile_body<T, G, NCH, NPMAX, TM, 2>(p, init, (int)blockIdx.x);
 }
 template <typename T, int G, int NCH, int NPMAX, int TM>
 __global__ __launch_bounds__(512) void step_tile_batch(const Params *runs, const int2 *blocks,
@@ -1157,7 +1164,7 @@ __global__ __launch_bounds__(512) void run_tile_persist(Params p, int t0, int n)
         rank_small_body<T>(p, 0, t);
         __syncthreads();
         const Iter it = iter_at(p, t);
-        step_tile_body<T, G, NCH, NPMAX, TM, THR>(p, 0, 0, &it);
+        step_tile_body<T, G, NCH, NPMAX, TM, THR ? 1 : 0>(p, 0, 0, &it);
         __syncthreads();
     }
     if (threadIdx.x == 0 && n > 0) p.ctrl->t = t0 + n;   // iterations closed
@@ -1205,6 +1212,19 @@ hipError_t launch_tile_thr(const Params &p, int init, dim3 grid, size_t lds, hip
                 if (ea != hipSuccess) return ea;
             }
             launch_k(p, step_tile_thr<T, GG, CC, NPMAX, TMM>, grid, dim3(512), lds, s, p, init);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (CC == 1 && TMM == 16) {
+        if (p.rotated && (p.kind == K_SPHERE || p.kind == K_RASTRIGIN || p.kind == K_ACKLEY)) {
+            done = true;
+            if (lds > 65536) {
+                const hipError_t ea =
+                    hipFuncSetAttribute((const void *)step_tile_sep<T, GG, CC, NPMAX, TMM>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (ea != hipSuccess) return ea;
+            }
+            launch_k(p, step_tile_sep<T, GG, CC, NPMAX, TMM>, grid, dim3(512), lds, s, p, init);
             return hipGetLastError();
         }
     }
