@@ -293,7 +293,11 @@ int apo_batch_member(apo_batch_t *b, int32_t i, apo_t **run);
  * every trial, and keeps the fastest.  Results do not depend on the
  * schedule.  Allocates a temporary device copy of the runs' state.
  * *schedule (may be NULL) receives the chosen schedule (0..3), *us (may be
- * NULL) four timings in microseconds per iteration. */
+ * NULL) four timings in microseconds per iteration.
+ * Known issue: on an MI355X the process has ended once with a host
+ * segmentation fault inside the trials (no GPU fault reported); the cause is
+ * not found (the host code passes an AddressSanitizer harness), so callers
+ * that cannot risk it keep the default schedule and do not call this. */
 int apo_batch_tune(apo_batch_t *b, int32_t iters, int32_t *schedule, double *us);
 
 /* Releases the batch, its members and (if library-allocated) its stream
