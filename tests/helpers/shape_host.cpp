@@ -5,6 +5,9 @@
 //   S es dim G NCH TM built fits key decoded_G decoded_NCH decoded_TM
 // then, for the batch policy (rotated; separable or Rosenbrock):
 //   P es dim rosenbrock G NCH TM fits
+// then, for the persistent elementwise form at its largest population
+// (256 / G protozoa), the LDS image of the run and its regions' offsets:
+//   I es dim G pop bytes x0 x1 f fs perm drf pdr lb ub sh
 #include <cstdio>
 
 #include "apo_shape.hpp"
@@ -37,5 +40,13 @@ int main() {
                 const bool fits = NCH > 0 && tile_shape_ok(dim, G, NCH, TM, es);
                 std::printf("P %d %d %d %d %d %d %d\n", es, dim, ros, G, NCH, TM, fits ? 1 : 0);
             }
+    for (int es = 4; es <= 8; es += 4)
+        for (int dim = 1; dim <= 1024; ++dim) {
+            const int G = lanes_for_dim(dim), pop = 256 / G;
+            const PersistImage m = persist_image(pop, row_stride(dim, es), es, false);
+            std::printf("I %d %d %d %d %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", es, dim, G,
+                        pop, m.total, m.x0, m.x1, m.f, m.fs, m.perm, m.drf, m.pdr, m.lb, m.ub,
+                        m.sh);
+        }
     return 0;
 }

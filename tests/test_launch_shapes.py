@@ -33,7 +33,8 @@ def table(tmp_path_factory):
     lines = out.splitlines()
     shapes = np.array([[int(v) for v in ln.split()[1:]] for ln in lines if ln.startswith("S ")])
     policy = np.array([[int(v) for v in ln.split()[1:]] for ln in lines if ln.startswith("P ")])
-    return shapes, policy
+    image = np.array([[int(v) for v in ln.split()[1:]] for ln in lines if ln.startswith("I ")])
+    return shapes, policy, image
 
 
 def test_shape_key_round_trips(table):
@@ -118,3 +119,21 @@ def test_batch_layout_accepts_every_policy_dimension():
             desc[0].opt.objective.kind = kind
             desc[0].opt.objective.rot = _lib._dptr(rot)
             assert L.apo_batch_workspace_bytes(1, desc) > 0, (kind, d)
+
+
+def test_persistent_lds_image_fits_and_is_disjoint(table):
+    """The persistent elementwise form keeps a run's state in LDS: at the
+    largest population it takes (256 / G protozoa) and every dimension up to
+    1024, the image plus the sort's and masks' static LDS fits one workgroup,
+    and its regions are 16-byte aligned, in order, and each as large as the
+    array it holds."""
+    image = table[2]
+    limit, static = 163840, 16384
+    for es, dim, G, pop, total, x0, x1, f, fs, perm, drf, pdr, lb, ub, sh in image:
+        Dp = (dim + 64 // es - 1) // (64 // es) * (64 // es)
+        offs = [x0, x1, f, fs, perm, drf, pdr, lb, ub, sh, total]
+        sizes = [pop * Dp * es, pop * Dp * es, pop * es, pop * es, pop * 4, pop, pop * 8,
+                 Dp * es, Dp * es, Dp * es]
+        assert all(o % 16 == 0 for o in offs)
+        assert all(offs[i] + sizes[i] <= offs[i + 1] for i in range(len(sizes)))
+        assert total + static <= limit, (es, dim, total)
