@@ -19,9 +19,10 @@ namespace apok {
 
 // ---------------------------------------------------------------------------
 // Rank sort.  rank(i) = #{j : (F_j, j) before (F_i, i)} in the fitness order,
-// so perm[rank(i)] = i.  One workgroup of 256 threads ranks 8 protozoa.
+// so perm[rank(i)] = i.  One workgroup of NT threads (512 for a single run,
+// 256 in batches) ranks 8 protozoa.
 // Each thread holds the order keys of its share of the population in
-// registers (j = tid, tid + 256, ...), compares them against the 8 keys
+// registers (j = tid, tid + NT, ...), compares them against the 8 keys
 // being ranked (read by LDS broadcast) and keeps 8 counters, which are
 // summed over the workgroup by butterflies and LDS at the end.  No
 // workgroup depends on another.  Each workgroup also opens the iteration
@@ -30,12 +31,13 @@ namespace apok {
 // of F) and whether the rank is in Dr.  Workgroup 0 publishes the
 // iteration in the control block.
 // ---------------------------------------------------------------------------
-constexpr int kRankJ = 16;        // keys per thread per pass (256 x 16 = 4096 per pass)
+constexpr int kRankPass = 4096;    // keys per pass (kRankPass / NT per thread)
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void rank_body(const Params &p, int blk) {
+    constexpr int kRankJ = kRankPass / NT, NW = NT / 64;
     __shared__ uint64_t s_ki[kRankPer];
-    __shared__ int32_t part[4][kRankPer];
+    __shared__ int32_t part[NW][kRankPer];
     __shared__ uint32_t s_keys[24];
     __shared__ int32_t s_mdr;
     const T *F = (const T *)p.F;
@@ -53,7 +55,7 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
     T fj[kRankJ];
 #pragma unroll
     for (int u = 0; u < kRankJ; ++u) {
-        const int j = 256 * u + tid;
+        const int j = NT * u + tid;
         fj[u] = F[j < ps ? j : ps - 1];
     }
     T fi = T(0);
@@ -70,11 +72,11 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
 #pragma unroll
     for (int q = 0; q < kRankPer; ++q) ki[q] = s_ki[q];
 
-    for (int base = 0; base < ps; base += 256 * kRankJ) {
+    for (int base = 0; base < ps; base += kRankPass) {
         if (base > 0) {   // further passes (ps above 4096)
 #pragma unroll
             for (int u = 0; u < kRankJ; ++u) {
-                const int j = base + 256 * u + tid;
+                const int j = base + NT * u + tid;
                 fj[u] = F[j < ps ? j : ps - 1];
             }
         }
@@ -83,14 +85,14 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
         uint64_t kj[kRankJ];
 #pragma unroll
         for (int u = 0; u < kRankJ; ++u) {
-            const int j = base + 256 * u + tid;
+            const int j = base + NT * u + tid;
             const uint64_t k = RankKey<T>::make(fj[u], j);
             kj[u] = j < ps ? k : ~0ull;   // ~0 sorts after all
         }
 #pragma unroll
         for (int u = 0; u < kRankJ; ++u) {
-            if (base + 256 * u >= ps) break;   // the rest of the pass is padding
-            const int j = base + 256 * u + tid;
+            if (base + NT * u >= ps) break;   // the rest of the pass is padding
+            const int j = base + NT * u + tid;
 #pragma unroll
             for (int q = 0; q < kRankPer; ++q)
                 cnt[q] += RankKey<T>::before(kj[u], j, ki[q], i0 + q) ? 1 : 0;
@@ -106,7 +108,9 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
     }
     __syncthreads();
     if (tid < kRankPer && i0 + tid < ps) {
-        const int rank = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+        int rank = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) rank += part[w][tid];
         p.perm[rank] = i0 + tid;
         ((T *)p.Fs)[rank] = fi;
         // Dr of Algorithm 1: rank r belongs iff pi(r) < |Dr|
@@ -128,17 +132,19 @@ __device__ __forceinline__ void rank_body(const Params &p, int blk) {
 // The LDS form of the sort (rank_small_body) is in apo_step.hpp: the persistent
 // form of small runs uses it too.
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void rank_any(const Params &p, int blk) {
     if (p.rank_lds)
         rank_small_body<T>(p, blk);
     else
-        rank_body<T>(p, blk);
+        rank_body<T, NT>(p, blk);
 }
 
+// A single run: 512 threads a workgroup (its LDS form, pop <= 256, ranks
+// with the first 256).
 template <typename T>
-__global__ __launch_bounds__(256) void rank_kernel(Params p) {
-    rank_any<T>(p, (int)blockIdx.x);
+__global__ __launch_bounds__(512) void rank_kernel(Params p) {
+    rank_any<T, 512>(p, (int)blockIdx.x);
 }
 
 // Several runs in one launch: workgroup b sorts block blocks[b].y of run
@@ -146,7 +152,7 @@ __global__ __launch_bounds__(256) void rank_kernel(Params p) {
 template <typename T>
 __global__ __launch_bounds__(256) void rank_kernel_batch(const Params *runs, const int2 *blocks) {
     const int2 b = blocks[blockIdx.x];
-    rank_any<T>(runs[b.x], b.y);
+    rank_any<T, 256>(runs[b.x], b.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,7 +373,7 @@ hipError_t launch_step(const Params &p, bool fp64, hipStream_t s) {
 }
 
 hipError_t launch_rank(const Params &p, bool fp64, hipStream_t s) {
-    const dim3 grid((unsigned)rank_blocks(p)), block(256);
+    const dim3 grid((unsigned)rank_blocks(p)), block(512);
     if (fp64)
         launch_k(p, rank_kernel<double>, grid, block, 0, s, p);
     else

@@ -160,11 +160,12 @@ __device__ __forceinline__ void rank_small_body(const Params &p, int blk, int t_
 #pragma unroll
     for (int u = 0; u < kRankSmall / 256; ++u) {
         const int j = tid + 256 * u;
-        if (j < ps) s_k[j] = RankKey<T>::make(f[u], j);
+        if (j < ps && tid < 256) s_k[j] = RankKey<T>::make(f[u], j);
     }
     __syncthreads();
+    // threads past 256 (workgroups of 512) take no part in the ranking
     const int i = blk * 256 + tid;
-    if (i < ps) {
+    if (i < ps && tid < 256) {
         const uint64_t ki = s_k[i];
         int rank = 0;
         for (int j = 0; j < ps; ++j) rank += RankKey<T>::before(s_k[j], j, ki, i) ? 1 : 0;
