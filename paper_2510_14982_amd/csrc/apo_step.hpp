@@ -369,13 +369,15 @@ __device__ __forceinline__ void plan_pairs(const Params &p, int r, int t, const 
     }
 }
 
-template <typename T, int NPMAX, int G>
+// ALLOW_ILP false: one position a lane per round always (the same set; the
+// four-position form is then not compiled in).
+template <typename T, int NPMAX, int G, bool ALLOW_ILP = true>
 __device__ __forceinline__ void plan_mask(const Params &p, Plan<T, NPMAX> &c, uint32_t *mwords,
                                           int lane) {
     c.mw = mwords;
     // four positions a lane per round where the scan spans eight or more
     // rounds of G positions, or where the run is one workgroup (latency only)
-    const bool ilp = c.mask.walk >= 8u * G || (long long)p.pop * G <= 256;
+    const bool ilp = ALLOW_ILP && (c.mask.walk >= 8u * G || (long long)p.pop * G <= 256);
     if (c.op != OP_DORMANCY)
         subset_mask_group<G>(c.mask, c.m, mwords, (p.dim + 31) / 32, lane,
                              (int)(threadIdx.x & 63) & ~(G - 1), ilp);
@@ -920,7 +922,9 @@ __device__ __forceinline__ void step_tile_body(const Params &p, int init, int bl
                 plan_decide<T, NPMAX>(p, item, it, d, c);   // while the ids load
                 plan_pick<T, NPMAX>(d, c);
                 load_rows<T, NPMAX, NCH, G>(p, c, lane, Xc, rw);
-                plan_mask<T, NPMAX, G>(p, c, s_mwords[grp], lane);   // while the rows load
+                // (the separable form's shapes, one chunk of at most 128
+                // coordinates in 16-row tiles, scan few rounds)
+                plan_mask<T, NPMAX, G, !SEP>(p, c, s_mwords[grp], lane);   // while the rows load
                 plan_pairs<T, NPMAX>(p, item, t, d, c);
             }
 #pragma unroll
